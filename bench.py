@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the spectral-element Poisson hot path on one MI355X.
+
+Workload (synthetic, seeded): the 32x32x32 brick of E = 32768 hexahedra on
+the unit cube at N = 10 GLL nodes per direction, deformed by
+x = X + 0.05 sin(2 pi X) sin(2 pi Y) sin(2 pi Z) (likewise y, z), so every
+node carries the full six geometric factors in FP64; u ~ U[-1, 1] (seed 0).
+
+One timed step is one application of the matrix-free operator
+w_e = D^T G_e D u_e to every element (the paper's AX kernel, Section II-B,
+Listing 1), with u, G, D and w resident in HBM.  The value is AX GFLOP/s
+counted with the paper's 12N + 11 flops per node (203 per node at 16 nodes
+per direction, Section III).  The same run also measures, on the same
+mesh with the manufactured sine right-hand side, the FP64 Jacobi-PCG
+time to a 1e-10 relative residual (and the mixed-precision solve when the
+library provides it), a plain streaming copy as the achievable-bandwidth
+reference, and the CPU oracle on a bounded sample on the host cores.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the solver measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--n", type=int, default=32, help="elements per brick edge")
+    ap.add_argument("--N", type=int, default=10, help="GLL nodes per direction")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2011_04981_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_hash):
+    """Counter-measured HBM bytes per AX launch, if profiles/ holds a record
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ax_f64_c2_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import synthetic as S
+    import paper_2011_04981_amd as nbx
+
+    dev = "cuda"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    brick = S.Brick(a.n, a.n, a.n, a.N, ((0.05, 2, 2, 2),) * 3, "sine", 0,
+                    f"deformed_E{a.n**3}_N{a.N}")
+    N, E = brick.N, brick.E
+    flops = nbx.ax_flops(N, E)
+    abytes = nbx.ax_bytes(N, E)
+    out = {}
+
+    with torch.cuda.stream(stream):
+        log(f"set-up: E={E} N={N}")
+        D = nbx.deriv_device(N, dev)
+        G, bm, _ = nbx.geom_brick(brick.ex, brick.ey, brick.ez, N, brick.deform_array())
+        u = torch.as_tensor(S.uniform_field(E, N, seed=0)).to(dev)
+        w = torch.empty_like(u)
+        stream.synchronize()
+
+        # ---- AX: warm-up, then exactly `steps` timed launches
+        for _ in range(a.warmup):
+            nbx.ax(u, G, D, out=w)
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(a.steps)]
+        t_all0 = torch.cuda.Event(enable_timing=True)
+        t_all1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        t_all0.record(stream)
+        for k in range(a.steps):
+            ev[k][0].record(stream)
+            nbx.ax(u, G, D, out=w)
+            ev[k][1].record(stream)
+        t_all1.record(stream)
+        torch.cuda.synchronize()
+        h1 = time.perf_counter()
+        per = [s.elapsed_time(e) * 1e-3 for s, e in ev]          # seconds per launch
+        total = t_all0.elapsed_time(t_all1) * 1e-3
+        mean_launch = statistics.fmean(per)
+        log(f"AX: mean {mean_launch*1e6:.1f} us  median {statistics.median(per)*1e6:.1f} us  "
+            f"min {min(per)*1e6:.1f} us  host {1e6*(h1-h0)/a.steps:.1f} us/step")
+
+        # ---- achievable-bandwidth reference: streaming copy of 1 GiB
+        n_copy = (1 << 30) // 8
+        src = torch.empty(n_copy, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            nbx.copy_f64(src, dst)
+        c0 = torch.cuda.Event(enable_timing=True); c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(10):
+            nbx.copy_f64(src, dst)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * 8 * n_copy * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        del src, dst
+        log(f"copy: {copy_gbs:.0f} GB/s")
+
+    ax_hash = src_hash("ax.hip")
+    achieved = abytes / mean_launch / 1e9
+    value = flops * a.steps / total / 1e9
+    out.update({
+        "metric": "AX GFLOP/s + % HBM roofline at N=10; PCG time-to-1e-10 vs plain FP64 Jacobi",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(total / a.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"AX on a {a.n}x{a.n}x{a.n} deformed brick (E={E}), N={N}, "
+                               "full 6-factor G in FP64, u~U[-1,1] seed 0",
+                   "E": E, "N": N, "flops_per_step": flops, "hbm_bytes_per_step": abytes},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_record(ax_hash),
+                     "kernel": "ax_col<double,10>", "kernel_source_hash": ax_hash,
+                     "mean_launch_us": round(mean_launch * 1e6, 2),
+                     "median_launch_us": round(statistics.median(per) * 1e6, 2),
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
+    })
+    del u, w, G, bm
+    torch.cuda.empty_cache()
+
+    # ---- solver: FP64 Jacobi-PCG to 1e-10 (and mixed precision if present)
+    if not a.no_pcg:
+        with torch.cuda.stream(stream):
+            log("solver set-up")
+            st = nbx.setup_brick(brick.ex, brick.ey, brick.ez, N, brick.deform_array())
+            stream.synchronize()
+            pcg = {}
+            x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, check_every=20)
+            times = []
+            for _ in range(3):
+                h0 = time.perf_counter()
+                x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, check_every=20)
+                times.append(time.perf_counter() - h0)
+            pcg["fp64"] = {"iters": r.iters, "seconds": round(min(times), 5),
+                           "loop_seconds": round(r.seconds, 5), "relres": r.relres,
+                           "true_relres": r.true_relres, "status": r.status}
+            log(f"FP64 PCG: {r.iters} it, {min(times):.4f} s, true relres {r.true_relres:.2e}")
+            x64 = x.clone()
+            _, r100 = st.problem.pcg(st.b, max_iter=100, fixed_iters=1, check_every=20)
+            pcg["fp64_100_iterations_seconds"] = round(r100.seconds, 5)
+            pcg["ms_per_iteration"] = round(r100.seconds / 100 * 1e3, 4)
+            try:
+                times = []
+                for _ in range(3):
+                    h0 = time.perf_counter()
+                    xm, rm = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32,
+                                            inner_rtol=1e-5, check_every=20)
+                    times.append(time.perf_counter() - h0)
+                err = float((xm - x64).abs().max() / x64.abs().max())
+                pcg["mixed_fp32"] = {"iters": rm.iters, "outer": rm.outer_iters,
+                                     "seconds": round(min(times), 5),
+                                     "true_relres": rm.true_relres,
+                                     "err_vs_fp64": err, "status": rm.status,
+                                     "speedup_vs_fp64": round(pcg["fp64"]["seconds"] /
+                                                              min(times), 3)}
+                log(f"mixed: {rm.iters} it / {rm.outer_iters} outer, {min(times):.4f} s")
+            except nbx.NbxError as e:
+                pcg["mixed_fp32"] = {"unavailable": str(e)}
+            out["pcg"] = pcg
+            del st, x, x64
+            torch.cuda.empty_cache()
+
+    # ---- CPU oracle baseline (host cores, bounded sample)
+    if not a.no_cpu:
+        import oracle as O
+        ez = max(1, 4096 // (a.n * a.n))
+        sb = S.Brick(a.n, a.n, ez, N, brick.deform, "sine", 0)
+        xi, wq = O.gll(N)
+        Do = O.deriv(N, xi)
+        Go, _, _ = O.geom(N, Do, wq, *O.brick_coords(sb, xi))
+        uo = S.uniform_field(sb.E, N, seed=0)
+        O.ax(uo, Go, Do)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < a.cpu_seconds and reps < 1000:
+            O.ax(uo, Go, Do)
+            reps += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(nbx.ax_flops(N, sb.E) * reps / dt / 1e9, 3), "unit": "GFLOP/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"oracle AX on {sb.E} elements ({a.n}x{a.n}x{ez} slab of the same "
+                      f"deformed mapping, N={N}), {reps} applications in {dt:.1f} s"}
+        log(f"cpu oracle: {out['cpu_baseline']['value']} GFLOP/s on {O.num_threads()} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * nbx.h -- C ABI of libnbx, the MI355X (gfx950) library for the
+ * spectral-element Poisson hot path studied in N. Brown, "Exploring the
+ * acceleration of Nekbone on reconfigurable architectures" (arXiv
+ * 2011.04981): the matrix-free operator AX (Section II-B, Listing 1),
+ * direct stiffness summation, and the Jacobi-preconditioned conjugate
+ * gradient solve built on them (Section II-B: CG with a simple
+ * preconditioner, nearest-neighbour exchange and global reductions).
+ *
+ * General conventions (every entry point):
+ *   - Return value: an nbx_status (0 = NBX_OK).  No C++ exception crosses
+ *     this boundary.  After NBX_EHIP, nbx_last_hip_error() gives the raw
+ *     hipError_t.
+ *   - Pointers named *_host are host memory; every other array pointer is
+ *     device memory (hipMalloc / torch CUDA tensors), 16-byte aligned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls documented "async" only enqueue work on `stream` and return;
+ *     they never allocate or synchronise.
+ *   - The caller owns every array it passes.  The library owns only what a
+ *     *_create call allocates, released by the matching *_destroy.
+ *   - A handle must not be used from two host threads at once.
+ *
+ * Layouts (Section II-B, Listing 1, column-major u(i,j,k,e)):
+ *   u, w, vectors : [E][N][N][N], i fastest: u[((e*N + k)*N + j)*N + i]
+ *   G             : [E][6][N^3]; factor f holds g_(f+1) of the listing, the
+ *                   symmetric matrix [[g1,g2,g3],[g2,g4,g5],[g3,g5,g6]]
+ *   D             : N x N row-major, D[a*N + b] = l_b'(xi_a) (the
+ *                   listing's dxm1; its transpose dxtm1 is derived inside)
+ *   N             : Gauss-Lobatto-Legendre nodes per direction (degree N-1),
+ *                   2 <= N <= 16.
+ *   Brick meshes  : element (a,b,c) of an ex x ey x ez brick on [0,1]^3 is
+ *                   e = a + ex*(b + ey*c).
+ */
+#ifndef NBX_H
+#define NBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { NBX_F64 = 0, NBX_F32 = 1, NBX_BF16 = 2, NBX_F16 = 3 } nbx_prec;
+
+typedef enum {
+    NBX_OK = 0,
+    NBX_NOT_CONVERGED = 1,   /* solve hit max_iter before rtol */
+    NBX_EINVAL = -1,         /* bad argument (null pointer, N out of range, E < 0) */
+    NBX_EUNSUPPORTED = -2,   /* valid but not implemented (precision, size) */
+    NBX_EHIP = -3,           /* a HIP runtime call failed */
+    NBX_ENOMEM = -4,         /* a *_create allocation failed */
+    NBX_EBREAKDOWN = -5      /* CG breakdown: <p,Ap> <= 0, <r,z> <= 0 or non-finite */
+} nbx_status;
+
+/* Text for a status code (static storage). */
+const char *nbx_status_str(int status);
+/* Raw hipError_t of the most recent NBX_EHIP on this thread. */
+int nbx_last_hip_error(void);
+/* Library version, 100*major + minor. */
+int nbx_version(void);
+
+/* dst[0..n) = src[0..n) with 16-byte accesses (a plain streaming copy of
+ * known size: the reference point for achievable HBM bandwidth and for
+ * calibrating hardware byte counters).  Async.  src, dst device, no
+ * overlap. */
+int nbx_copy_f64(const double *src, double *dst, int64_t n, void *stream);
+
+/* ------------------------------------------------------------ set-up --
+ * The paper names the geometry ("block or linear geometry", Section II-B)
+ * but not its discretisation; these calls build it with the standard
+ * spectral-element definitions. */
+
+/* Gauss-Lobatto-Legendre nodes xi_host[N] (ascending, -1..1) and weights
+ * w_host[N].  Host only.  NBX_EINVAL if N < 2 or N > 16. */
+int nbx_gll(int N, double *xi_host, double *w_host);
+
+/* Derivative matrix D_host[N*N] (row-major, D[a*N+b] = l_b'(xi_a)) for the
+ * GLL nodes.  Host only. */
+int nbx_deriv(int N, double *D_host);
+
+/* Geometric factors of a deformed brick, computed on the device (async).
+ * deform_host[12] = {A_x,k1,k2,k3, A_y,k1,k2,k3, A_z,k1,k2,k3}: coordinate
+ * c of the node at undeformed position (X,Y,Z) is
+ * C + A_c sin(k1 pi X) sin(k2 pi Y) sin(k3 pi Z).  Outputs (device):
+ * G[E][6][N^3] = w_i w_j w_k det(J) (grad r_a . grad r_b) from
+ * isoparametric derivatives, bm[E][N^3] = w_i w_j w_k det(J) (may be NULL),
+ * xyz[3][E][N^3] node coordinates (may be NULL). */
+int nbx_geom_brick(int ex, int ey, int ez, int N, const double *deform_host,
+                   double *G, double *bm, double *xyz, void *stream);
+
+/* Same factors from arbitrary node coordinates xyz[3][E][N^3] (device,
+ * async).  bm may be NULL. */
+int nbx_geom(const double *xyz, int N, int64_t E, double *G, double *bm, void *stream);
+
+/* Global node ids of the brick's local nodes (gid_host[E*N^3]) and the
+ * homogeneous Dirichlet flags (bnd_host[E*N^3] = 1 on the cube's
+ * boundary).  Host only. */
+int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host, uint8_t *bnd_host);
+
+/* ---------------------------------------------------------------- AX --
+ * w_e = D^T G_e D u_e for every element e in [0,E) (Section II-B,
+ * Listing 1: local_grad3, the geometric contraction, local_grad3_t).
+ * Async; no allocation.  prec selects the storage and arithmetic type of
+ * u, G, w: NBX_F64 (double), NBX_F32 (float, FP32 arithmetic).  D is always
+ * double (converted inside).  u and w must not overlap.  E == 0 is a no-op.
+ * NBX_EINVAL for null pointers, N outside [2,16] or E < 0;
+ * NBX_EUNSUPPORTED for other precisions. */
+int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
+           void *w, void *stream);
+
+/* ------------------------------------------------ gather-scatter (dssum) --
+ * The "nearest-neighbour communication" step of a CG iteration (Section
+ * II-B), on one GPU: local copies of a global node are summed and the sum
+ * written back to every copy. */
+typedef struct nbx_gs nbx_gs;
+
+/* Builds the gather-scatter plan from host global ids (gid_host[n_local],
+ * equal ids = same global node) and Dirichlet flags (bnd_host, may be NULL
+ * for none).  Allocates device arrays; synchronous.  NBX_EUNSUPPORTED if
+ * n_local >= 2^31 or a node has more than 127 copies. */
+int nbx_gs_create(const int64_t *gid_host, const uint8_t *bnd_host, int64_t n_local,
+                  nbx_gs **out);
+int nbx_gs_destroy(nbx_gs *gs);
+
+/* In place: v_l <- sum of v over l's global node, summed in ascending local
+ * index (every copy gets identical bits).  apply_mask != 0 then zeroes
+ * Dirichlet nodes.  Async; prec NBX_F64 or NBX_F32. */
+int nbx_dssum(nbx_gs *gs, int prec, void *v, int apply_mask, void *stream);
+
+/* Multiplicity (number of copies) of every local node as double, device
+ * out[n_local].  Async. */
+int nbx_gs_multiplicity(nbx_gs *gs, double *out, void *stream);
+
+/* ------------------------------------------------------------ Jacobi --
+ * The "simple preconditioner" (Section II-B) read as Jacobi: dinv =
+ * 1 / dssum(diag(A_e)), 0 on Dirichlet nodes.  Async. */
+int nbx_jacobi_setup(const double *G, const double *D, int N, int64_t E, nbx_gs *gs,
+                     double *dinv, void *stream);
+
+/* Manufactured source f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) at the nodes
+ * xyz[3][n] (device), for which u* = sin(pi x) sin(pi y) sin(pi z) solves
+ * -lap u = f with u = 0 on the unit cube's boundary.  Async. */
+int nbx_sine_source(const double *xyz, int64_t n, double *f, void *stream);
+
+/* Assembled load vector b = mask(dssum(bm * f)) for nodal source values f
+ * (device, [E][N^3]).  Async. */
+int nbx_rhs(nbx_gs *gs, const double *bm, const double *f, int64_t n_local, double *b,
+            void *stream);
+
+/* --------------------------------------------------------------- PCG -- */
+typedef struct nbx_problem nbx_problem;
+
+/* Binds G, D, N, E and a gather-scatter plan (all remain caller-owned and
+ * must outlive the problem), computes dinv on the device and allocates the
+ * solver workspace (four vectors, reduction partials, scalars).
+ * Synchronous.  NBX_ENOMEM if device memory runs out. */
+int nbx_problem_create(const double *G, const double *D, int N, int64_t E, nbx_gs *gs,
+                       nbx_problem **out, void *stream);
+int nbx_problem_destroy(nbx_problem *p);
+/* Copies the problem's dinv into out[n_local] (device).  Async. */
+int nbx_problem_dinv(nbx_problem *p, double *out, void *stream);
+
+/* Length of the device scalar block used by nbx_pcg_iterate. */
+#define NBX_SCAL_LEN 16
+/* scal[] slots: */
+#define NBX_S_RHO 0      /* <r,z>_c */
+#define NBX_S_BETA 1     /* beta applied at the start of the next iteration */
+#define NBX_S_ALPHA 2
+#define NBX_S_PAP 3      /* <p,Ap>_c */
+#define NBX_S_RR 4       /* <r,r>_c after the last iteration */
+#define NBX_S_BB 5       /* <b,b>_c */
+#define NBX_S_STOP 6     /* stop when RR <= STOP (negative: never) */
+#define NBX_S_FLAG 7     /* 0 running, 1 converged, 2 breakdown, 3 MAXIT reached */
+#define NBX_S_ITER 8     /* iterations completed */
+#define NBX_S_MAXIT 9    /* FLAG becomes 3 when ITER reaches this */
+
+/* Advances a Jacobi-PCG state by up to n_iter iterations (async; no
+ * allocation).  State on entry: x, r, z (= dinv r), p (previous search
+ * direction; finite), scal[RHO] = <r,z>_c, scal[BETA], scal[STOP],
+ * scal[FLAG] = 0.  Each iteration:
+ *   p = z + beta p;  w = mask(dssum(AX(p)));  alpha = rho / <p,w>_c;
+ *   x += alpha p;  r -= alpha w;  stop if <r,r>_c <= STOP;
+ *   z = dinv r;  rho' = <r,z>_c;  beta = rho'/rho.
+ * <a,b>_c weights each local node by 1/multiplicity.  Once FLAG != 0 the
+ * remaining iterations do nothing (FLAG = 3 when ITER reaches MAXIT).
+ * Vectors are [E][N^3] doubles; every vector and scal must be distinct
+ * from the problem's own workspace. */
+int nbx_pcg_iterate(nbx_problem *p, double *x, double *r, double *z, double *pdir,
+                    double *scal, int n_iter, void *stream);
+
+typedef struct {
+    int max_iter;        /* iteration cap (default 1000) */
+    int fixed_iters;     /* nonzero: run exactly max_iter iterations, no test */
+    int check_every;     /* iterations per graph launch between host checks */
+    int use_graph;       /* nonzero: replay iterations from a captured hipGraph */
+    double rtol;         /* stop when ||r||_c <= rtol ||b||_c */
+    int prec;            /* NBX_F64: plain FP64 PCG; NBX_F32: FP32 inner PCG in
+                            FP64 iterative refinement */
+    double inner_rtol;   /* inner relative tolerance for refinement */
+    int max_outer;       /* refinement cap */
+} nbx_pcg_opts;
+
+typedef struct {
+    int iters;           /* total (inner) CG iterations */
+    int outer_iters;     /* refinement steps (1 for plain PCG) */
+    double relres;       /* ||r||_c / ||b||_c of the recurrence residual */
+    double true_relres;  /* ||b - A x||_c / ||b||_c recomputed in FP64 */
+    int fell_back;       /* a fallback solver was used */
+    int flag;            /* 0 limit, 1 converged, 2 breakdown */
+    double seconds;      /* wall time of the iteration loop */
+} nbx_pcg_result;
+
+/* Fills opts with defaults. */
+void nbx_pcg_default_opts(nbx_pcg_opts *opts);
+
+/* Solves A x = b from x = 0 (b, x device [E][N^3] doubles).  Synchronous:
+ * returns after convergence, breakdown or max_iter, with res filled.
+ * Returns NBX_OK, NBX_NOT_CONVERGED or NBX_EBREAKDOWN. */
+int nbx_pcg(nbx_problem *p, const double *b, double *x, const nbx_pcg_opts *opts,
+            nbx_pcg_result *res, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBX_H */

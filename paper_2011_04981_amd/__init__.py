@@ -1,0 +1,397 @@
+"""MI355X-native spectral-element Poisson hot path (matrix-free AX, dssum,
+Jacobi-PCG) -- Python binding of libnbx.
+
+This module only marshals arguments into the C ABI declared in
+include/nbx.h; every step of the computation runs in the library's HIP
+kernels.  torch supplies device memory and streams.  If libnbx.so has not
+been built the import of any compute entry point fails loudly: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbx.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+SCAL_LEN = 16
+S_RHO, S_BETA, S_ALPHA, S_PAP, S_RR, S_BB, S_STOP, S_FLAG, S_ITER, S_MAXIT = range(10)
+
+STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "unsupported",
+          -3: "HIP error", -4: "out of memory", -5: "CG breakdown"}
+
+
+class NbxError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status})")
+
+
+_lib = None
+
+
+class PcgOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
+                ("use_graph", C.c_int), ("rtol", C.c_double), ("prec", C.c_int),
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int)]
+
+
+class PcgResult(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer_iters", C.c_int), ("relres", C.c_double),
+                ("true_relres", C.c_double), ("fell_back", C.c_int), ("flag", C.c_int),
+                ("seconds", C.c_double)]
+
+
+def lib():
+    """The loaded libnbx (raises if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                           "(python paper_2011_04981_amd/build.py) first")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "nbx_status_str": ([i32], C.c_char_p),
+        "nbx_last_hip_error": ([], i32),
+        "nbx_version": ([], i32),
+        "nbx_copy_f64": ([vp, vp, i64, vp], i32),
+        "nbx_gll": ([i32, vp, vp], i32),
+        "nbx_deriv": ([i32, vp], i32),
+        "nbx_geom_brick": ([i32, i32, i32, i32, vp, vp, vp, vp, vp], i32),
+        "nbx_geom": ([vp, i32, i64, vp, vp, vp], i32),
+        "nbx_brick_ids": ([i32, i32, i32, i32, vp, vp], i32),
+        "nbx_ax": ([i32, vp, vp, vp, i32, i64, vp, vp], i32),
+        "nbx_gs_create": ([vp, vp, i64, C.POINTER(vp)], i32),
+        "nbx_gs_destroy": ([vp], i32),
+        "nbx_dssum": ([vp, i32, vp, i32, vp], i32),
+        "nbx_gs_multiplicity": ([vp, vp, vp], i32),
+        "nbx_jacobi_setup": ([vp, vp, i32, i64, vp, vp, vp], i32),
+        "nbx_rhs": ([vp, vp, vp, i64, vp, vp], i32),
+        "nbx_sine_source": ([vp, i64, vp, vp], i32),
+        "nbx_problem_create": ([vp, vp, i32, i64, vp, C.POINTER(vp), vp], i32),
+        "nbx_problem_destroy": ([vp], i32),
+        "nbx_problem_dinv": ([vp, vp, vp], i32),
+        "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
+        "nbx_pcg_default_opts": ([C.POINTER(PcgOpts)], None),
+        "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str) -> int:
+    if st < 0:
+        raise NbxError(st, what)
+    return st
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t, dtype=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (checked)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def copy_f64(src, dst, stream=None):
+    """dst <- src with the library's streaming copy kernel."""
+    torch = _torch()
+    if src.numel() != dst.numel():
+        raise ValueError("size mismatch")
+    _check(lib().nbx_copy_f64(_dptr(src, torch.float64), _dptr(dst, torch.float64),
+                              src.numel(), _stream(stream)), "nbx_copy_f64")
+    return dst
+
+
+# ----------------------------------------------------------------- set-up
+
+def gll(N: int):
+    xi = np.zeros(N); w = np.zeros(N)
+    _check(lib().nbx_gll(N, _hptr(xi), _hptr(w)), "nbx_gll")
+    return xi, w
+
+
+def deriv(N: int) -> np.ndarray:
+    D = np.zeros((N, N))
+    _check(lib().nbx_deriv(N, _hptr(D)), "nbx_deriv")
+    return D
+
+
+def deriv_device(N: int, device="cuda"):
+    return _torch().from_numpy(deriv(N)).to(device)
+
+
+def geom_brick(ex: int, ey: int, ez: int, N: int, deform=None, with_xyz=False,
+               device="cuda", stream=None):
+    """(G [E,6,N^3], bm [E,N^3], xyz [3,E,N^3] or None) for a deformed brick,
+    computed on the device."""
+    torch = _torch()
+    E = ex * ey * ez
+    N3 = N ** 3
+    G = torch.empty((E, 6, N3), dtype=torch.float64, device=device)
+    bm = torch.empty((E, N3), dtype=torch.float64, device=device)
+    xyz = torch.empty((3, E, N3), dtype=torch.float64, device=device) if with_xyz else None
+    d = np.ascontiguousarray(deform if deform is not None else
+                             [[0, 1, 1, 1]] * 3, dtype=np.float64).reshape(12)
+    _check(lib().nbx_geom_brick(ex, ey, ez, N, _hptr(d), _dptr(G), _dptr(bm),
+                                _dptr(xyz) if xyz is not None else None, _stream(stream)),
+           "nbx_geom_brick")
+    return G, bm, xyz
+
+
+def geom(xyz, N: int, stream=None):
+    torch = _torch()
+    E = xyz.shape[1]
+    G = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=xyz.device)
+    bm = torch.empty((E, N ** 3), dtype=torch.float64, device=xyz.device)
+    _check(lib().nbx_geom(_dptr(xyz, torch.float64, "xyz"), N, E, _dptr(G), _dptr(bm),
+                          _stream(stream)), "nbx_geom")
+    return G, bm
+
+
+def brick_ids(ex: int, ey: int, ez: int, N: int):
+    n = ex * ey * ez * N ** 3
+    gid = np.zeros(n, dtype=np.int64); bnd = np.zeros(n, dtype=np.uint8)
+    _check(lib().nbx_brick_ids(ex, ey, ez, N, _hptr(gid), _hptr(bnd)), "nbx_brick_ids")
+    return gid, bnd
+
+
+# --------------------------------------------------------------------- AX
+
+def ax(u, G, D, N: Optional[int] = None, out=None, stream=None):
+    """w = AX(u) for u [E, N^3] (float64 or float32), G [E, 6, N^3] of the
+    same dtype, D [N, N] float64 (device)."""
+    torch = _torch()
+    N = D.shape[0] if N is None else N
+    E = u.numel() // N ** 3
+    prec = {torch.float64: F64, torch.float32: F32}.get(u.dtype)
+    if prec is None:
+        raise TypeError(f"unsupported dtype {u.dtype}")
+    if G.dtype != u.dtype:
+        raise TypeError("G and u must share a dtype")
+    if G.numel() != 6 * u.numel():
+        raise ValueError("G must hold 6 factors per node")
+    w = torch.empty_like(u) if out is None else out
+    _check(lib().nbx_ax(prec, _dptr(u, name="u"), _dptr(G, name="G"),
+                        _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
+                        _stream(stream)), "nbx_ax")
+    return w
+
+
+# --------------------------------------------------------- gather-scatter
+
+class GS:
+    """dssum plan built from host global ids and Dirichlet flags."""
+
+    def __init__(self, gid: np.ndarray, bnd: Optional[np.ndarray] = None):
+        gid = np.ascontiguousarray(gid, dtype=np.int64).reshape(-1)
+        self.n = gid.size
+        b = None if bnd is None else np.ascontiguousarray(bnd, dtype=np.uint8).reshape(-1)
+        h = C.c_void_p()
+        _check(lib().nbx_gs_create(_hptr(gid), _hptr(b) if b is not None else None,
+                                   self.n, C.byref(h)), "nbx_gs_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbx_gs_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dssum(self, v, mask: bool = True, stream=None):
+        torch = _torch()
+        prec = {torch.float64: F64, torch.float32: F32}[v.dtype]
+        _check(lib().nbx_dssum(self._h, prec, _dptr(v), 1 if mask else 0, _stream(stream)),
+               "nbx_dssum")
+        return v
+
+    def multiplicity(self, device="cuda", stream=None):
+        torch = _torch()
+        m = torch.empty(self.n, dtype=torch.float64, device=device)
+        _check(lib().nbx_gs_multiplicity(self._h, _dptr(m), _stream(stream)),
+               "nbx_gs_multiplicity")
+        return m
+
+
+def jacobi_setup(G, D, gs: GS, N: int, stream=None):
+    torch = _torch()
+    E = G.shape[0]
+    dinv = torch.empty((E, N ** 3), dtype=torch.float64, device=G.device)
+    _check(lib().nbx_jacobi_setup(_dptr(G, torch.float64), _dptr(D, torch.float64), N, E,
+                                  gs.handle, _dptr(dinv), _stream(stream)), "nbx_jacobi_setup")
+    return dinv
+
+
+def sine_source(xyz, stream=None):
+    """f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) at the nodes xyz [3, ...]."""
+    torch = _torch()
+    n = xyz[0].numel()
+    f = torch.empty(xyz.shape[1:], dtype=torch.float64, device=xyz.device)
+    _check(lib().nbx_sine_source(_dptr(xyz, torch.float64, "xyz"), n, _dptr(f),
+                                 _stream(stream)), "nbx_sine_source")
+    return f
+
+
+def rhs(gs: GS, bm, f, stream=None):
+    torch = _torch()
+    b = torch.empty_like(bm)
+    _check(lib().nbx_rhs(gs.handle, _dptr(bm, torch.float64), _dptr(f, torch.float64),
+                         bm.numel(), _dptr(b), _stream(stream)), "nbx_rhs")
+    return b
+
+
+# -------------------------------------------------------------------- PCG
+
+def default_opts(**kw) -> PcgOpts:
+    o = PcgOpts()
+    lib().nbx_pcg_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iters: int
+    outer_iters: int
+    relres: float
+    true_relres: float
+    fell_back: int
+    flag: int
+    seconds: float
+
+
+class Problem:
+    """Binds (G, D, N, E, gs); owns dinv and the solver workspace."""
+
+    def __init__(self, G, D, N: int, gs: GS, stream=None):
+        torch = _torch()
+        self.G, self.D, self.N, self.gs = G, D, N, gs
+        self.E = G.shape[0]
+        h = C.c_void_p()
+        _check(lib().nbx_problem_create(_dptr(G, torch.float64), _dptr(D, torch.float64), N,
+                                        self.E, gs.handle, C.byref(h), _stream(stream)),
+               "nbx_problem_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbx_problem_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dinv(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.E, self.N ** 3), dtype=torch.float64, device=self.G.device)
+        _check(lib().nbx_problem_dinv(self._h, _dptr(out), _stream(stream)), "nbx_problem_dinv")
+        return out
+
+    def pcg(self, b, x=None, stream=None, **opts) -> tuple:
+        torch = _torch()
+        x = torch.empty_like(b) if x is None else x
+        o = default_opts(**opts)
+        r = PcgResult()
+        st = lib().nbx_pcg(self._h, _dptr(b, torch.float64, "b"), _dptr(x, torch.float64, "x"),
+                           C.byref(o), C.byref(r), _stream(stream))
+        if st < 0 and st != -5:
+            raise NbxError(st, "nbx_pcg")
+        return x, SolveResult(st, r.iters, r.outer_iters, r.relres, r.true_relres,
+                              r.fell_back, r.flag, r.seconds)
+
+    def pcg_iterate(self, x, r, z, p, scal, n_iter: int, stream=None):
+        torch = _torch()
+        _check(lib().nbx_pcg_iterate(self._h, _dptr(x, torch.float64), _dptr(r, torch.float64),
+                                     _dptr(z, torch.float64), _dptr(p, torch.float64),
+                                     _dptr(scal, torch.float64), n_iter, _stream(stream)),
+               "nbx_pcg_iterate")
+
+
+def ax_flops(N: int, E: int) -> int:
+    """E N^3 (12N + 11): the paper's per-point operation count (203 at 16
+    nodes per direction, Section III)."""
+    return E * N ** 3 * (12 * N + 11)
+
+
+def ax_bytes(N: int, E: int, itemsize: int = 8) -> int:
+    """Algorithmic HBM bytes of one AX: u, six factors and w per node."""
+    return E * N ** 3 * 8 * itemsize
+
+
+@dataclass
+class BrickSetup:
+    """Device-side set-up of a brick problem: geometry, numbering, the
+    gather-scatter plan, the solver problem and the load vector."""
+    N: int
+    E: int
+    D: object
+    G: object
+    bm: object
+    xyz: object
+    gs: GS
+    problem: Problem
+    b: object
+
+
+def setup_brick(ex: int, ey: int, ez: int, N: int, deform=None, f=None, device="cuda",
+                stream=None) -> BrickSetup:
+    """Builds a brick problem on the device.  f: nodal source values (torch
+    float64 [E, N^3] on the device) or None for the manufactured sine
+    source."""
+    torch = _torch()
+    D = deriv_device(N, device)
+    G, bm, xyz = geom_brick(ex, ey, ez, N, deform, with_xyz=True, device=device, stream=stream)
+    gid, bnd = brick_ids(ex, ey, ez, N)
+    gs = GS(gid, bnd)
+    P = Problem(G, D, N, gs, stream=stream)
+    if f is None:
+        f = sine_source(xyz, stream=stream)
+    b = rhs(gs, bm, f, stream=stream)
+    return BrickSetup(N, ex * ey * ez, D, G, bm, xyz, gs, P, b)

@@ -1,0 +1,69 @@
+// abi.hip -- status codes, error capture and version of the C ABI.
+#include "internal.hpp"
+
+namespace nbx {
+
+static thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_last_hip_error = (int)e;
+    (void)what;
+    return NBX_EHIP;
+}
+
+}  // namespace nbx
+
+extern "C" const char *nbx_status_str(int st)
+{
+    switch (st) {
+        case NBX_OK: return "ok";
+        case NBX_NOT_CONVERGED: return "not converged (iteration limit)";
+        case NBX_EINVAL: return "invalid argument";
+        case NBX_EUNSUPPORTED: return "unsupported configuration";
+        case NBX_EHIP: return "HIP runtime error";
+        case NBX_ENOMEM: return "out of device memory";
+        case NBX_EBREAKDOWN: return "CG breakdown";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int nbx_last_hip_error(void) { return nbx::g_last_hip_error; }
+
+extern "C" int nbx_version(void) { return 100; }
+
+namespace {
+
+__global__ void __launch_bounds__(256)
+copy_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2;
+         q += (int64_t)gridDim.x * blockDim.x)
+        dst[q] = src[q];
+}
+
+__global__ void copy_tail_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                                 int64_t n)
+{
+    if (threadIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
+}
+
+}  // namespace
+
+extern "C" int nbx_copy_f64(const double *src, double *dst, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!src || !dst))) return NBX_EINVAL;
+    if (n == 0) return NBX_OK;
+    hipStream_t s = nbx::as_stream(stream);
+    const int64_t n2 = n >> 1;
+    if (n2 > 0) {
+        int64_t blocks = (n2 + 255) / 256;
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const double2 *>(src),
+                           reinterpret_cast<double2 *>(dst), n2);
+    }
+    if (n & 1) hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, src, dst, n);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}

@@ -1,0 +1,174 @@
+// gs.hip -- direct stiffness summation (dssum) and the Dirichlet mask.
+//
+// The paper's CG iteration includes a nearest-neighbour exchange (Section
+// II-B) that makes the element-local copies of every shared node agree; on
+// one GPU that is this gather-scatter.  The plan lists only nodes with
+// more than one copy (a brick at N = 10 shares under half of its local
+// nodes), grouped by global node with local indices ascending, so every
+// group sums in a fixed order and writes identical bits to all copies:
+// no atomics, deterministic, and bit-identical to a sequential sum in
+// ascending local order.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+namespace nbx {
+namespace {
+
+template <typename T>
+__global__ void dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off,
+                             const int32_t *__restrict__ idx, const uint8_t *__restrict__ gflag,
+                             T *__restrict__ v, int apply_mask, const double *__restrict__ flag)
+{
+    if (flag && *flag != 0.0) return;   // uniform: solve already finished
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const int32_t b = off[g], e = off[g + 1];
+    T s = 0;
+    for (int32_t q = b; q < e; ++q) s += v[idx[q]];
+    if (apply_mask && gflag[g]) s = 0;
+    for (int32_t q = b; q < e; ++q) v[idx[q]] = s;
+}
+
+template <typename T>
+__global__ void mask_only_kernel(int32_t n, const int32_t *__restrict__ idx, T *__restrict__ v,
+                                 const double *__restrict__ flag)
+{
+    if (flag && *flag != 0.0) return;
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) v[idx[q]] = 0;
+}
+
+__global__ void multiplicity_kernel(int64_t n, const uint8_t *__restrict__ info,
+                                    double *__restrict__ out)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n) out[l] = (double)(info[l] & 0x7f);
+}
+
+template <typename T>
+void *dev_upload(const std::vector<T> &h, int &st)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { st = NBX_ENOMEM; return nullptr; }
+    if (!h.empty()) {
+        e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); hipFree(p); return nullptr; }
+    }
+    return p;
+}
+
+void free_plan(GsPlan &p)
+{
+    hipFree(p.off); hipFree(p.idx); hipFree(p.gflag); hipFree(p.mask_idx); hipFree(p.info);
+    p = GsPlan{};
+}
+
+}  // namespace
+
+template <typename T>
+int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const double *flag)
+{
+    if (gs.n_groups > 0) {
+        hipLaunchKernelGGL(dssum_kernel<T>, dim3((gs.n_groups + 255) / 256), dim3(256), 0, s,
+                           gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask, flag);
+        NBX_LAUNCH_CHECK();
+    }
+    if (apply_mask && gs.n_mask_only > 0) {
+        hipLaunchKernelGGL(mask_only_kernel<T>, dim3((gs.n_mask_only + 255) / 256), dim3(256),
+                           0, s, gs.n_mask_only, gs.mask_idx, v, flag);
+        NBX_LAUNCH_CHECK();
+    }
+    return NBX_OK;
+}
+
+template int dssum_launch<double>(const GsPlan &, double *, int, hipStream_t, const double *);
+template int dssum_launch<float>(const GsPlan &, float *, int, hipStream_t, const double *);
+
+}  // namespace nbx
+
+using namespace nbx;
+
+extern "C" int nbx_gs_create(const int64_t *gid_host, const uint8_t *bnd_host, int64_t n_local,
+                             nbx_gs **out)
+{
+    if (!out || n_local < 0 || (n_local > 0 && !gid_host)) return NBX_EINVAL;
+    *out = nullptr;
+    if (n_local >= 0x7fffffffLL) return NBX_EUNSUPPORTED;
+    const int32_t n = (int32_t)n_local;
+    // order local nodes by (global id, local index)
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return gid_host[a] < gid_host[b]; });
+    std::vector<int32_t> off{0}, idx, mask_idx;
+    std::vector<uint8_t> gflag, info(n, 0);
+    for (int32_t q = 0; q < n;) {
+        int32_t r = q;
+        uint8_t bnd = 0;
+        while (r < n && gid_host[order[r]] == gid_host[order[q]]) {
+            if (bnd_host && bnd_host[order[r]]) bnd = 1;
+            ++r;
+        }
+        const int32_t m = r - q;
+        if (m > 127) return NBX_EUNSUPPORTED;
+        for (int32_t t = q; t < r; ++t) info[order[t]] = (uint8_t)(m | (bnd ? 0x80 : 0));
+        if (m >= 2) {
+            for (int32_t t = q; t < r; ++t) idx.push_back(order[t]);
+            off.push_back((int32_t)idx.size());
+            gflag.push_back(bnd);
+        } else if (bnd) {
+            mask_idx.push_back(order[q]);
+        }
+        q = r;
+    }
+    nbx_gs *gs = new (std::nothrow) nbx_gs;
+    if (!gs) return NBX_ENOMEM;
+    GsPlan &p = gs->plan;
+    p.n_local = n_local;
+    p.n_groups = (int32_t)gflag.size();
+    p.n_mask_only = (int32_t)mask_idx.size();
+    int st = NBX_OK;
+    p.off = (int32_t *)dev_upload(off, st);
+    if (st == NBX_OK) p.idx = (int32_t *)dev_upload(idx, st);
+    if (st == NBX_OK) p.gflag = (uint8_t *)dev_upload(gflag, st);
+    if (st == NBX_OK) p.mask_idx = (int32_t *)dev_upload(mask_idx, st);
+    if (st == NBX_OK) p.info = (uint8_t *)dev_upload(info, st);
+    if (st != NBX_OK) { free_plan(p); delete gs; return st; }
+    *out = gs;
+    return NBX_OK;
+}
+
+extern "C" int nbx_gs_destroy(nbx_gs *gs)
+{
+    if (!gs) return NBX_OK;
+    free_plan(gs->plan);
+    delete gs;
+    return NBX_OK;
+}
+
+extern "C" int nbx_dssum(nbx_gs *gs, int prec, void *v, int apply_mask, void *stream)
+{
+    if (!gs || (!v && gs->plan.n_local > 0)) return NBX_EINVAL;
+    hipStream_t s = as_stream(stream);
+    switch (prec) {
+        case NBX_F64: return dssum_launch<double>(gs->plan, (double *)v, apply_mask, s);
+        case NBX_F32: return dssum_launch<float>(gs->plan, (float *)v, apply_mask, s);
+        default: return NBX_EUNSUPPORTED;
+    }
+}
+
+extern "C" int nbx_gs_multiplicity(nbx_gs *gs, double *out, void *stream)
+{
+    if (!gs || (!out && gs->plan.n_local > 0)) return NBX_EINVAL;
+    const int64_t n = gs->plan.n_local;
+    if (n == 0) return NBX_OK;
+    hipLaunchKernelGGL(multiplicity_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       as_stream(stream), n, gs->plan.info, out);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}

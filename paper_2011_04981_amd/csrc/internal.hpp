@@ -1,0 +1,71 @@
+// internal.hpp -- shared declarations of libnbx's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/nbx.h"
+
+namespace nbx {
+
+// Records the HIP error for nbx_last_hip_error() and returns NBX_EHIP.
+int hip_fail(hipError_t e, const char *what);
+
+#define NBX_HIP(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::nbx::hip_fail(e_, #call);   \
+    } while (0)
+
+#define NBX_LAUNCH_CHECK()                                         \
+    do {                                                           \
+        hipError_t e_ = hipGetLastError();                         \
+        if (e_ != hipSuccess) return ::nbx::hip_fail(e_, "launch");\
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int kMaxN = 16;
+
+// GLL nodes / weights / derivative matrix computed on the host.
+int gll_host(int N, double *xi, double *w);
+void deriv_host(int N, const double *xi, double *D);
+
+// Gather-scatter plan (device arrays).
+struct GsPlan {
+    int64_t n_local = 0;
+    int32_t n_groups = 0;       // shared groups (>= 2 copies)
+    int32_t n_mask_only = 0;    // Dirichlet nodes with a single copy
+    int32_t *off = nullptr;     // [n_groups+1]
+    int32_t *idx = nullptr;     // [off[n_groups]] local indices
+    uint8_t *gflag = nullptr;   // [n_groups] 1 = Dirichlet group
+    int32_t *mask_idx = nullptr;// [n_mask_only]
+    uint8_t *info = nullptr;    // [n_local] bits 0..6 multiplicity, bit 7 Dirichlet
+};
+
+// Enqueue dssum on a double or float vector.  With `flag` (device), the
+// kernels do nothing once *flag != 0 (a finished solve).
+template <typename T>
+int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s,
+                 const double *flag = nullptr);
+
+// AX launch (double / float).
+int ax_launch_f64(const double *u, const double *G, const double *D, int N, int64_t E,
+                  double *w, hipStream_t s);
+int ax_launch_f32(const float *u, const float *G, const double *D, int N, int64_t E,
+                  float *w, hipStream_t s);
+
+// Fused PCG first stage: p = z + beta p; w = AX(p); part[blk] = sum p*w.
+int ax_pcg_launch_f64(const double *G, const double *D, int N, int64_t E, const double *z,
+                      double *p, double *w, double *part, const double *scal, hipStream_t s);
+
+// Jacobi diagonal of each element (unassembled).
+int jacobi_diag_launch(const double *G, const double *D, int N, int64_t E, double *diag,
+                       hipStream_t s);
+
+}  // namespace nbx
+
+struct nbx_gs {
+    nbx::GsPlan plan;
+};

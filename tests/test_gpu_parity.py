@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance for FP64 results: normwise relative 1e-12,
+max|gpu - oracle| <= 1e-12 * max|oracle| (pointwise relative error is
+meaningless where AX cancels, e.g. AX(const) = 0).  dssum sums in the same
+ascending order as the oracle, so it must agree bit for bit.  Each side
+builds its own GLL rule, D and geometric factors from the same workload
+description; the shared inputs are the seeded random fields only.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2011_04981_amd as nbx  # noqa: E402
+
+DEV = "cuda"
+TOL = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def assert_rel(a, b, tol):
+    e = rel(a, b)
+    assert e <= tol, f"normwise relative error {e:.3e} > {tol:.1e}"
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# --------------------------------------------------------------------- AX
+
+@pytest.mark.parametrize("N,E", [(2, 1), (3, 5), (4, 37), (5, 3), (6, 64), (7, 9), (8, 33),
+                                 (9, 2), (10, 1), (10, 129), (11, 4), (12, 17), (13, 2),
+                                 (14, 3), (15, 2), (16, 5)])
+def test_ax_random_factors(N, E):
+    print(f"ax parity N={N} E={E}", flush=True)
+    u = S.uniform_field(E, N, seed=N)
+    G = S.random_factors(E, N, seed=N + 1)
+    want = O.ax(u, G, O.deriv(N))
+    got = host(nbx.ax(cuda(u), cuda(G), nbx.deriv_device(N)))
+    assert_rel(got, want, TOL)
+
+
+def test_ax_zero_elements_is_noop():
+    w = torch.full((0, 1000), 7.0, dtype=torch.float64, device=DEV)
+    u = torch.zeros((0, 1000), dtype=torch.float64, device=DEV)
+    G = torch.zeros((0, 6, 1000), dtype=torch.float64, device=DEV)
+    D = nbx.deriv_device(10)
+    assert nbx.lib().nbx_ax(0, nbx._dptr(torch.zeros(1, dtype=torch.float64, device=DEV)),
+                            nbx._dptr(torch.zeros(1, dtype=torch.float64, device=DEV)),
+                            nbx._dptr(D), 10, 0,
+                            nbx._dptr(torch.zeros(2, dtype=torch.float64, device=DEV)),
+                            None) == 0
+    del w, u, G
+
+
+@pytest.mark.parametrize("dims,N", [((3, 3, 3), 10), ((2, 3, 4), 6), ((4, 2, 2), 12)])
+def test_geometry_and_ax_on_deformed_mesh(dims, N):
+    """Each side builds G from the C2 mapping; factors, mass and AX agree."""
+    print(f"deformed geometry dims={dims} N={N}", flush=True)
+    b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
+    P = O.setup(b)
+    G, bm, xyz = nbx.geom_brick(*dims, N, b.deform_array(), with_xyz=True)
+    assert_rel(host(G), P.G, TOL)
+    assert_rel(host(bm), P.bm, TOL)
+    assert_rel(host(xyz)[0], P.x, 1e-15)
+    u = S.uniform_field(b.E, N, seed=3)
+    got = host(nbx.ax(cuda(u), G, nbx.deriv_device(N)))
+    assert_rel(got, O.ax(u, P.G, P.D), TOL)
+
+
+def test_ax_full_size_deformed_c2():
+    """The benchmark workload itself (E = 32768, N = 10, launch as timed),
+    checked on every element."""
+    b = S.c2_brick()
+    N = b.N
+    print("ax parity at E=32768 N=10", flush=True)
+    G, bm, _ = nbx.geom_brick(b.ex, b.ey, b.ez, N, b.deform_array())
+    xi, wq = O.gll(N)
+    D = O.deriv(N, xi)
+    x, y, z = O.brick_coords(b, xi)
+    Go, bmo, _ = O.geom(N, D, wq, x, y, z)
+    del x, y, z
+    assert_rel(host(G), Go, TOL)
+    u = S.uniform_field(b.E, N, seed=0)
+    w = nbx.ax(cuda(u), G, nbx.deriv_device(N))
+    assert_rel(host(w), O.ax(u, Go, D), TOL)
+
+
+def test_ax_is_deterministic():
+    N, E = 10, 300
+    u = cuda(S.uniform_field(E, N, 5)); G = cuda(S.random_factors(E, N, 6))
+    D = nbx.deriv_device(N)
+    a = host(nbx.ax(u, G, D)); b = host(nbx.ax(u, G, D))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N", [4, 8, 10, 12])
+def test_ax_fp32_error_vs_oracle(N):
+    """FP32 storage and arithmetic: error reported against the FP64 oracle,
+    gated at a bound of a few hundred FP32 ulps of the result scale."""
+    E = 40
+    u = S.uniform_field(E, N, seed=11)
+    G = S.random_factors(E, N, seed=12)
+    want = O.ax(u, G, O.deriv(N))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
+    err = rel(got, want)
+    print(f"fp32 AX N={N}: normwise error {err:.3e}")
+    assert err <= 300 * np.finfo(np.float32).eps
+
+
+# ---------------------------------------------------- dssum / mask / Jacobi
+
+@pytest.mark.parametrize("dims,N", [((3, 4, 5), 5), ((4, 4, 4), 10), ((2, 2, 1), 2)])
+def test_dssum_bit_exact(dims, N):
+    b = S.Brick(*dims, N)
+    gid, bnd = nbx.brick_ids(*dims, N)
+    gs = nbx.GS(gid, bnd)
+    ogs = O.GS(O.brick_ids(b)[0])
+    v = S.uniform_field(b.E, N, seed=21).reshape(-1)
+    for mask in (False, True):
+        t = cuda(v)
+        gs.dssum(t, mask=mask)
+        want = ogs.dssum(v)
+        if mask:
+            want = O.mask(bnd, want)
+        assert np.array_equal(host(t), want), mask
+    np.testing.assert_array_equal(host(gs.multiplicity()), ogs.multiplicity())
+
+
+def test_dssum_fp32_matches_fp32_sum():
+    b = S.Brick(3, 2, 2, 6)
+    gid, bnd = nbx.brick_ids(3, 2, 2, 6)
+    gs = nbx.GS(gid, bnd)
+    v = S.uniform_field(b.E, 6, seed=2).reshape(-1).astype(np.float32)
+    t = cuda(v, torch.float32)
+    gs.dssum(t, mask=True)
+    want = O.mask(bnd, O.GS(gid).dssum(v.astype(np.float64)))
+    assert_rel(host(t), want, 4 * np.finfo(np.float32).eps)
+
+
+@pytest.mark.parametrize("dims,N", [((3, 3, 3), 10), ((2, 3, 2), 7)])
+def test_jacobi_and_rhs(dims, N):
+    b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
+    P = O.setup(b)
+    st = nbx.setup_brick(*dims, N, b.deform_array())
+    assert_rel(host(st.problem.dinv()), P.dinv, TOL)
+    assert_rel(host(st.b), P.b, TOL)
+
+
+# -------------------------------------------------------------------- PCG
+
+def _gpu_state(st, x, r, p, rho):
+    """Device state for one nbx_pcg_iterate step that starts from the
+    oracle's (x, r, p, rho): z := p and beta = 0 make the kernel's
+    p = z + beta p reproduce the oracle's search direction exactly."""
+    n = st.E * st.N ** 3
+    xs, rs = cuda(x).reshape(st.E, -1), cuda(r).reshape(st.E, -1)
+    zs = cuda(p).reshape(st.E, -1)
+    ps = torch.zeros_like(zs)
+    scal = torch.zeros(nbx.SCAL_LEN, dtype=torch.float64, device=DEV)
+    scal[nbx.S_RHO] = rho
+    scal[nbx.S_STOP] = -1.0
+    scal[nbx.S_MAXIT] = 1e9
+    return xs, rs, zs, ps, scal
+
+
+@pytest.mark.parametrize("case", ["c1", "deformed8"])
+def test_pcg_one_step_parity(case):
+    b = S.c1_brick() if case == "c1" else S.scaled_c2_brick(3, 8)
+    P = O.setup(b)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    state = O.pcg_start(P)
+    done = 0
+    for k in (0, 1, 10, 50):
+        if k > done:
+            x, r, z, p, rho, *_ = O.pcg_iterate(P, state, k - done)
+            state = (x, r, z, p, rho)
+            done = k
+        print(f"one-step parity {case} k={k}", flush=True)
+        xs, rs, zs, ps, scal = _gpu_state(st, state[0], state[1], state[3], state[4])
+        st.problem.pcg_iterate(xs, rs, zs, ps, scal, 1)
+        x1, r1, z1, p1, rho1, it, flag, _ = O.pcg_iterate(P, state, 1)
+        sc = host(scal)
+        assert sc[nbx.S_FLAG] == 0 and sc[nbx.S_ITER] == 1
+        assert_rel(host(xs), x1, TOL)
+        assert_rel(host(rs), r1, TOL)
+        assert_rel(host(zs), z1, TOL)
+        assert abs(sc[nbx.S_RHO] - rho1) <= TOL * abs(rho1)
+        pnext = host(zs + sc[nbx.S_BETA] * ps)
+        assert_rel(pnext, p1, TOL)
+
+
+def test_pcg_100_iterations_c1():
+    b = S.c1_brick()
+    P = O.setup(b)
+    ora = O.pcg(P, max_iter=100, rtol=0.0)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N)
+    x, res = st.problem.pcg(st.b, max_iter=100, fixed_iters=1, check_every=10)
+    assert res.iters == 100 and ora.iters == 100
+    err = rel(host(x), ora.x)
+    print(f"C1 100-iteration x difference {err:.3e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_pcg_solve_to_1e10(graph):
+    b = S.scaled_c2_brick(4, 8)
+    P = O.setup(b)
+    ora = O.pcg(P, max_iter=2000, rtol=1e-10)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=2000, use_graph=graph, check_every=7)
+    print(f"solve: gpu {res.iters} it, oracle {ora.iters} it, true relres {res.true_relres:.2e}")
+    assert res.status == 0 and res.flag == 1
+    assert abs(res.iters - ora.iters) <= 1
+    assert res.relres <= 1e-10 and res.true_relres <= 1e-9
+    assert_rel(host(x), ora.x, 1e-8)
+
+
+def test_pcg_deterministic_and_reusable():
+    b = S.scaled_c2_brick(3, 6)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x1, r1 = st.problem.pcg(st.b, rtol=1e-10, check_every=5)
+    x2, r2 = st.problem.pcg(st.b, rtol=1e-10, check_every=5)
+    assert r1.iters == r2.iters
+    assert np.array_equal(host(x1), host(x2))
+
+
+def test_pcg_max_iter_limit_reports_not_converged():
+    b = S.scaled_c2_brick(3, 6)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, res = st.problem.pcg(st.b, rtol=1e-14, max_iter=7, check_every=3)
+    assert res.status == 1 and res.iters == 7 and res.flag == 0
+
+
+def test_pcg_zero_rhs_returns_zero():
+    b = S.Brick(2, 2, 2, 5)
+    st = nbx.setup_brick(2, 2, 2, 5)
+    zero = torch.zeros_like(st.b)
+    x, res = st.problem.pcg(zero, rtol=1e-10)
+    assert res.status == 0 and res.iters == 0
+    assert float(host(x).__abs__().max()) == 0.0
+
+
+def test_pcg_one_step_full_size_c2():
+    """One fused iteration on the full benchmark mesh from x = 0."""
+    b = S.c2_brick()
+    print("one-step parity at E=32768", flush=True)
+    P = O.setup(b)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    assert_rel(host(st.b), P.b, TOL)
+    state = O.pcg_start(P)
+    xs, rs, zs, ps, scal = _gpu_state(st, state[0], state[1], state[3], state[4])
+    st.problem.pcg_iterate(xs, rs, zs, ps, scal, 1)
+    x1, r1, z1, p1, rho1, *_ = O.pcg_iterate(P, state, 1)
+    assert_rel(host(xs), x1, TOL)
+    assert_rel(host(rs), r1, TOL)
+    assert abs(host(scal)[nbx.S_RHO] - rho1) <= TOL * abs(rho1)
