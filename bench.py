@@ -37,8 +37,8 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-pcg", action="store_true", help="skip the solver measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -141,7 +141,7 @@ def main():
         del src, dst
         log(f"copy: {copy_gbs:.0f} GB/s")
 
-    ax_hash = src_hash("ax.hip")
+    ax_hash = src_hash("ax_kernel.hpp", "ax_f64.hip", "ax.hip")
     achieved = abytes / mean_launch / 1e9
     value = flops * a.steps / total / 1e9
     out.update({
@@ -163,7 +163,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_record(ax_hash),
-                     "kernel": "ax_col<double,10>", "kernel_source_hash": ax_hash,
+                     "kernel": f"ax_kernel<double,{N},{nbx.get_tile(nbx.F64, N)},false>",
+                     "kernel_source_hash": ax_hash,
                      "mean_launch_us": round(mean_launch * 1e6, 2),
                      "median_launch_us": round(statistics.median(per) * 1e6, 2),
                      "copy_gbs": round(copy_gbs, 1),

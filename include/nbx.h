@@ -108,6 +108,18 @@ int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host, uint8_t *bnd
 int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
            void *w, void *stream);
 
+/* nbx_ax with an explicit tile: epb elements per workgroup (1, 2 or 4).
+ * Every tile computes bit-identical results; tiles differ only in speed.
+ * NBX_EINVAL for another epb, NBX_EUNSUPPORTED if the tile's LDS would
+ * exceed 160 KB. */
+int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
+                 void *w, int epb, void *stream);
+
+/* The tile nbx_ax and the solvers use for (prec, N) (process-wide; set by
+ * the autotuner).  get returns epb or a negative status. */
+int nbx_ax_set_tile(int prec, int N, int epb);
+int nbx_ax_get_tile(int prec, int N);
+
 /* ------------------------------------------------ gather-scatter (dssum) --
  * The "nearest-neighbour communication" step of a CG iteration (Section
  * II-B), on one GPU: local copies of a global node are summed and the sum

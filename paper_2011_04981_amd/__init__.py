@@ -69,6 +69,9 @@ def lib():
         "nbx_geom": ([vp, i32, i64, vp, vp, vp], i32),
         "nbx_brick_ids": ([i32, i32, i32, i32, vp, vp], i32),
         "nbx_ax": ([i32, vp, vp, vp, i32, i64, vp, vp], i32),
+        "nbx_ax_tiled": ([i32, vp, vp, vp, i32, i64, vp, i32, vp], i32),
+        "nbx_ax_set_tile": ([i32, i32, i32], i32),
+        "nbx_ax_get_tile": ([i32, i32], i32),
         "nbx_gs_create": ([vp, vp, i64, C.POINTER(vp)], i32),
         "nbx_gs_destroy": ([vp], i32),
         "nbx_dssum": ([vp, i32, vp, i32, vp], i32),
@@ -189,9 +192,10 @@ def brick_ids(ex: int, ey: int, ez: int, N: int):
 
 # --------------------------------------------------------------------- AX
 
-def ax(u, G, D, N: Optional[int] = None, out=None, stream=None):
+def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[int] = None):
     """w = AX(u) for u [E, N^3] (float64 or float32), G [E, 6, N^3] of the
-    same dtype, D [N, N] float64 (device)."""
+    same dtype, D [N, N] float64 (device).  epb forces a tile (elements per
+    workgroup); by default the library's tile table decides."""
     torch = _torch()
     N = D.shape[0] if N is None else N
     E = u.numel() // N ** 3
@@ -203,10 +207,23 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None):
     if G.numel() != 6 * u.numel():
         raise ValueError("G must hold 6 factors per node")
     w = torch.empty_like(u) if out is None else out
-    _check(lib().nbx_ax(prec, _dptr(u, name="u"), _dptr(G, name="G"),
-                        _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
-                        _stream(stream)), "nbx_ax")
+    if epb is None:
+        _check(lib().nbx_ax(prec, _dptr(u, name="u"), _dptr(G, name="G"),
+                            _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
+                            _stream(stream)), "nbx_ax")
+    else:
+        _check(lib().nbx_ax_tiled(prec, _dptr(u, name="u"), _dptr(G, name="G"),
+                                  _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
+                                  int(epb), _stream(stream)), "nbx_ax_tiled")
     return w
+
+
+def set_tile(prec: int, N: int, epb: int) -> None:
+    _check(lib().nbx_ax_set_tile(prec, N, epb), "nbx_ax_set_tile")
+
+
+def get_tile(prec: int, N: int) -> int:
+    return _check(lib().nbx_ax_get_tile(prec, N), "nbx_ax_get_tile")
 
 
 # --------------------------------------------------------- gather-scatter

@@ -34,12 +34,15 @@ extern "C" int nbx_version(void) { return 100; }
 
 namespace {
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// One 16-byte element per thread, non-temporal store (the fastest plain
+// copy measured on MI355X: ~6.4 TB/s for 0.8 GB each way).
 __global__ void __launch_bounds__(256)
-copy_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2)
+copy_kernel(const dbl2 *__restrict__ src, dbl2 *__restrict__ dst, int64_t n2)
 {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2;
-         q += (int64_t)gridDim.x * blockDim.x)
-        dst[q] = src[q];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n2) __builtin_nontemporal_store(src[q], dst + q);
 }
 
 __global__ void copy_tail_kernel(const double *__restrict__ src, double *__restrict__ dst,
@@ -57,11 +60,11 @@ extern "C" int nbx_copy_f64(const double *src, double *dst, int64_t n, void *str
     hipStream_t s = nbx::as_stream(stream);
     const int64_t n2 = n >> 1;
     if (n2 > 0) {
-        int64_t blocks = (n2 + 255) / 256;
-        if (blocks > 256 * 64) blocks = 256 * 64;
+        const int64_t blocks = (n2 + 255) / 256;
+        if (blocks > 0x7fffffffLL) return NBX_EUNSUPPORTED;
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                           reinterpret_cast<const double2 *>(src),
-                           reinterpret_cast<double2 *>(dst), n2);
+                           reinterpret_cast<const dbl2 *>(src), reinterpret_cast<dbl2 *>(dst),
+                           n2);
     }
     if (n & 1) hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, src, dst, n);
     NBX_LAUNCH_CHECK();

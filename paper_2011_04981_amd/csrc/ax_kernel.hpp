@@ -1,0 +1,254 @@
+// ax_kernel.hpp -- the matrix-free spectral-element operator
+// w_e = D^T G_e D u_e (Section II-B, Listing 1: local_grad3, the per-node
+// geometric contraction, local_grad3_t) as one gfx950 kernel template.
+//
+// Mapping: a workgroup takes EPB consecutive elements; element el's
+// N^2 (i,j) columns occupy lanes el*N^2 .. el*N^2 + N^2-1 (packed, the last
+// wave padded to 64 lanes).  Lane (i,j) of an element
+//   * keeps the k-column u(i,j,0..N-1) in registers, so the t-direction
+//     contractions never leave the register file;
+//   * stages its column in the element's LDS slab, from which the r and s
+//     contractions read row u(:,j,k) and column u(i,:,k);
+//   * writes wr, ws to two more LDS slabs for the transposed contractions
+//     and keeps wt in registers.
+// Memory order matters on MI355X's HBM3E: the u column is requested first,
+// then all 6N geometric factors of the column with non-temporal loads (75%
+// of the element's bytes, read exactly once), so that the first slab's
+// contractions overlap the factor stream; w is written with non-temporal
+// stores.  Measured on the 32^3 brick at N = 10 this order is worth ~20%
+// over plain loads and stores.  Uniform entries D[k][m] come through the
+// scalar cache (FP64) or as LDS broadcasts (FP32); per-lane rows and
+// columns of D sit in registers.
+#pragma once
+
+#include "internal.hpp"
+
+namespace nbx {
+
+template <int N, int EPB>
+struct AxShape {
+    static constexpr int N2 = N * N;
+    static constexpr int N3 = N2 * N;
+    static constexpr int NACT = EPB * N2;                 // active lanes
+    static constexpr int NT = ((NACT + 63) / 64) * 64;   // threads per block
+    // k-slabs of the column's six factors requested at entry and held in
+    // registers (6 PF values); the remaining slabs are loaded in the k
+    // loop.  The whole column fits up to N = 10 in FP64 (12N VGPRs) and
+    // N = 12 in FP32; larger elements keep the register file under 256.
+    template <typename T>
+    static constexpr int pf()
+    {
+        return sizeof(T) == sizeof(double) ? (N <= 10 ? N : (N <= 12 ? 6 : 4))
+                                           : (N <= 12 ? N : 8);
+    }
+    // LDS of one block: three element slabs per element, D, reduction slots.
+    template <typename T>
+    static constexpr bool fits()
+    {
+        return (3 * EPB * N3 + N2) * sizeof(T) + (NT / 64) * sizeof(double) <= 160 * 1024;
+    }
+};
+
+__device__ inline double ax_wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ inline T ax_ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ inline void ax_st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
+// Fused multiply-add written out: every instantiation (tile, fused or not)
+// then performs the same operation sequence and produces the same bits.
+__device__ inline double ax_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float ax_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// PCG == false: w = AX(u).
+// PCG == true : uin is z; p <- z + beta p (stored); w = AX(p);
+//               part[block] = sum over the block's elements of p*w
+//               (skipped entirely once scal[FLAG] != 0).
+template <typename T, int N, int EPB, bool PCG>
+__global__ void __launch_bounds__((AxShape<N, EPB>::NT))
+ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
+          T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
+          const double *__restrict__ scal, int64_t E)
+{
+#pragma clang fp contract(off)
+    using S = AxShape<N, EPB>;
+    constexpr int N2 = S::N2, N3 = S::N3, NT = S::NT, NACT = S::NACT;
+    constexpr bool kDLds = sizeof(T) != sizeof(double);   // uniform D from LDS
+    __shared__ T s_u[EPB * N3];
+    __shared__ T s_wr[EPB * N3];
+    __shared__ T s_ws[EPB * N3];
+    __shared__ T s_D[N2];
+    __shared__ double s_red[NT / 64];
+
+    if constexpr (PCG) {
+        if (scal[NBX_S_FLAG] != 0.0) return;   // uniform: solve finished
+    }
+    const int t = threadIdx.x;
+    const bool lane_act = t < NACT;
+    const int tl = lane_act ? t : NACT - 1;    // idle lanes shadow a real column
+    const int el = tl / N2, tc = tl - el * N2;
+    const int i = tc % N, j = tc / N;
+    const int64_t e_raw = (int64_t)blockIdx.x * EPB + el;
+    const bool valid = lane_act && e_raw < E;  // ragged last block
+    const int64_t e = e_raw < E ? e_raw : E - 1;
+    const size_t base = (size_t)e * N3;
+    const T *Ge = G + (size_t)e * 6 * N3;
+    T *su = s_u + el * N3, *swr = s_wr + el * N3, *sws = s_ws + el * N3;
+
+    // 1. the column of u (or of z and the previous p) first ...
+    T uc[N];
+    if constexpr (PCG) {
+        const T beta = (T)scal[NBX_S_BETA];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const T zv = uin[base + k * N2 + tc];
+            const T pv = pio[base + k * N2 + tc];
+            uc[k] = ax_fma(beta, pv, zv);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) uc[k] = uin[base + k * N2 + tc];
+    }
+    // 2. ... then every geometric factor of the column, streamed once
+    constexpr int PF = S::template pf<T>();
+    // factor-major order: consecutive requests cover consecutive addresses,
+    // so a line shared by two 8N^2-byte slabs is asked for twice in a row
+    T g[6][PF];
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int k = 0; k < PF; ++k) g[f][k] = ax_ld_nt(Ge + f * N3 + k * N2 + tc);
+    for (int q = t; q < N2; q += NT) s_D[q] = (T)Dg[q];
+    if constexpr (PCG) {
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) ax_st_nt(uc[k], pio + base + k * N2 + tc);
+        }
+    }
+    if (lane_act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) su[k * N2 + tc] = uc[k];
+    }
+    __syncthreads();
+
+    // 3. local_grad3 and the geometric contraction, slab by slab
+    T wt[N];
+    {
+        T Di[N], Dj[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) { Di[m] = s_D[i * N + m]; Dj[m] = s_D[j * N + m]; }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            T ur = 0, us = 0, ut = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) ur = ax_fma(Di[m], su[k * N2 + j * N + m], ur);
+#pragma unroll
+            for (int m = 0; m < N; ++m) us = ax_fma(Dj[m], su[k * N2 + m * N + i], us);
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                ut = ax_fma(kDLds ? s_D[k * N + m] : (T)Dg[k * N + m], uc[m], ut);
+            T g1, g2, g3, g4, g5, g6;
+            if (k < PF) {
+                g1 = g[0][k]; g2 = g[1][k]; g3 = g[2][k]; g4 = g[3][k]; g5 = g[4][k]; g6 = g[5][k];
+            } else {
+                const T *gp = Ge + k * N2 + tc;
+                g1 = ax_ld_nt(gp); g2 = ax_ld_nt(gp + N3); g3 = ax_ld_nt(gp + 2 * N3);
+                g4 = ax_ld_nt(gp + 3 * N3); g5 = ax_ld_nt(gp + 4 * N3); g6 = ax_ld_nt(gp + 5 * N3);
+            }
+            const T wr = ax_fma(g3, ut, ax_fma(g2, us, g1 * ur));
+            const T ws = ax_fma(g5, ut, ax_fma(g4, us, g2 * ur));
+            wt[k] = ax_fma(g6, ut, ax_fma(g5, us, g3 * ur));
+            if (lane_act) { swr[k * N2 + tc] = wr; sws[k * N2 + tc] = ws; }
+        }
+    }
+    __syncthreads();
+
+    // 4. local_grad3_t: w = D^T wr + (ws D per slab) + wt D
+    double pw = 0.0;
+    {
+        T DTi[N], DTj[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) { DTi[m] = s_D[m * N + i]; DTj[m] = s_D[m * N + j]; }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            T acc = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) acc = ax_fma(DTi[m], swr[k * N2 + j * N + m], acc);
+#pragma unroll
+            for (int m = 0; m < N; ++m) acc = ax_fma(DTj[m], sws[k * N2 + m * N + i], acc);
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                acc = ax_fma(kDLds ? s_D[m * N + k] : (T)Dg[m * N + k], wt[m], acc);
+            if (valid) ax_st_nt(acc, w + base + k * N2 + tc);
+            if constexpr (PCG) pw += (double)uc[k] * (double)acc;
+        }
+    }
+    if constexpr (PCG) {
+        if (!valid) pw = 0.0;
+        pw = ax_wave_sum(pw);
+        if ((t & 63) == 0) s_red[t >> 6] = pw;
+        __syncthreads();
+        if (t == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT / 64; ++q) s += s_red[q];
+            part[blockIdx.x] = s;
+        }
+    }
+}
+
+// Elements per workgroup the library may use (the autotuner's search space).
+constexpr int kEpbChoices[] = {1, 2, 4};
+
+template <typename T, bool PCG, int N>
+int ax_launch_epb(int epb, const T *u, const T *G, const double *D, T *w, T *p, double *part,
+                  const double *scal, int64_t E, hipStream_t s)
+{
+#define NBX_EPB_CASE(EE)                                                                     \
+    case EE: {                                                                               \
+        if constexpr (AxShape<N, EE>::template fits<T>()) {                                  \
+            constexpr int NT_ = AxShape<N, EE>::NT;                                          \
+            const int64_t nb = (E + EE - 1) / EE;                                            \
+            hipLaunchKernelGGL((ax_kernel<T, N, EE, PCG>), dim3((unsigned)nb), dim3(NT_), 0, \
+                               s, u, G, D, w, p, part, scal, E);                             \
+            return NBX_OK;                                                                   \
+        } else {                                                                             \
+            return NBX_EUNSUPPORTED;                                                         \
+        }                                                                                    \
+    }
+    switch (epb) {
+        NBX_EPB_CASE(1)
+        NBX_EPB_CASE(2)
+        NBX_EPB_CASE(4)
+        default: return NBX_EINVAL;
+    }
+#undef NBX_EPB_CASE
+}
+
+template <typename T, bool PCG>
+int ax_launch_any(int N, int epb, const T *u, const T *G, const double *D, T *w, T *p,
+                  double *part, const double *scal, int64_t E, hipStream_t s)
+{
+    if (E <= 0) return NBX_OK;
+    if ((E + epb - 1) / epb > 0x7fffffffLL) return NBX_EUNSUPPORTED;
+    int st;
+#define NBX_N_CASE(NN)                                                                     \
+    case NN: st = ax_launch_epb<T, PCG, NN>(epb, u, G, D, w, p, part, scal, E, s); break;
+    switch (N) {
+        NBX_N_CASE(2) NBX_N_CASE(3) NBX_N_CASE(4) NBX_N_CASE(5) NBX_N_CASE(6)
+        NBX_N_CASE(7) NBX_N_CASE(8) NBX_N_CASE(9) NBX_N_CASE(10) NBX_N_CASE(11)
+        NBX_N_CASE(12) NBX_N_CASE(13) NBX_N_CASE(14) NBX_N_CASE(15) NBX_N_CASE(16)
+        default: return NBX_EINVAL;
+    }
+#undef NBX_N_CASE
+    if (st != NBX_OK) return st;
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+}  // namespace nbx

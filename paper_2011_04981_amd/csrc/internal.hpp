@@ -57,8 +57,15 @@ int ax_launch_f32(const float *u, const float *G, const double *D, int N, int64_
                   float *w, hipStream_t s);
 
 // Fused PCG first stage: p = z + beta p; w = AX(p); part[blk] = sum p*w.
+// The number of partials written is ax_blocks(prec, N, E).
 int ax_pcg_launch_f64(const double *G, const double *D, int N, int64_t E, const double *z,
                       double *p, double *w, double *part, const double *scal, hipStream_t s);
+int ax_pcg_launch_f32(const float *G, const double *D, int N, int64_t E, const float *z,
+                      float *p, float *w, double *part, const double *scal, hipStream_t s);
+// Elements per workgroup currently selected for (prec, N), and the
+// resulting number of AX workgroups for E elements.
+int ax_tile(int prec, int N);
+int ax_blocks(int prec, int N, int64_t E);
 
 // Jacobi diagonal of each element (unassembled).
 int jacobi_diag_launch(const double *G, const double *D, int N, int64_t E, double *diag,

@@ -258,8 +258,8 @@ static int enqueue_iters(nbx_problem *P, double *x, double *r, double *z, double
     for (int it = 0; it < n_iter; ++it) {
         int st = ax_pcg_launch_f64(P->G, P->D, P->N, P->E, z, p, P->w, P->part1, scal, s);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(pap_reduce_kernel, dim3(1), dim3(1024), 0, s, (int)P->E, P->part1,
-                           scal);
+        hipLaunchKernelGGL(pap_reduce_kernel, dim3(1), dim3(1024), 0, s,
+                           ax_blocks(NBX_F64, P->N, P->E), P->part1, scal);
         st = dssum_launch<double>(gs, P->w, 1, s, scal + NBX_S_FLAG);
         if (st != NBX_OK) return st;
         hipLaunchKernelGGL(update_kernel, dim3(P->nb3), dim3(kRedThreads), 0, s, P->n, p, P->w,

@@ -88,12 +88,26 @@ def test_geometry_and_ax_on_deformed_mesh(dims, N):
     assert_rel(got, O.ax(u, P.G, P.D), TOL)
 
 
+def test_ax_full_size_seeded_factors():
+    """Benchmark size and launch (E = 32768, N = 10, the library's default
+    tile) on identical seeded inputs, checked on every element."""
+    N, E = 10, 32768
+    print("ax parity at E=32768 N=10 (seeded factors)", flush=True)
+    u = S.uniform_field(E, N, seed=0)
+    G = S.random_factors(E, N, seed=1)
+    w = nbx.ax(cuda(u), cuda(G), nbx.deriv_device(N))
+    assert_rel(host(w), O.ax(u, G, O.deriv(N)), TOL)
+
+
 def test_ax_full_size_deformed_c2():
-    """The benchmark workload itself (E = 32768, N = 10, launch as timed),
-    checked on every element."""
+    """The benchmark workload itself, each side with its own geometry.
+    The factors agree to 1e-12; AX of the two factor sets is compared at
+    1e-11 because the sides' sin() differ by an ulp in the coordinates and
+    the derivative stencil amplifies that by ~10^2 in G, and AX by another
+    order in w."""
     b = S.c2_brick()
     N = b.N
-    print("ax parity at E=32768 N=10", flush=True)
+    print("ax at E=32768 N=10 with each side's own geometry", flush=True)
     G, bm, _ = nbx.geom_brick(b.ex, b.ey, b.ez, N, b.deform_array())
     xi, wq = O.gll(N)
     D = O.deriv(N, xi)
@@ -101,9 +115,10 @@ def test_ax_full_size_deformed_c2():
     Go, bmo, _ = O.geom(N, D, wq, x, y, z)
     del x, y, z
     assert_rel(host(G), Go, TOL)
+    assert_rel(host(bm), bmo, TOL)
     u = S.uniform_field(b.E, N, seed=0)
     w = nbx.ax(cuda(u), G, nbx.deriv_device(N))
-    assert_rel(host(w), O.ax(u, Go, D), TOL)
+    assert_rel(host(w), O.ax(u, Go, D), 1e-11)
 
 
 def test_ax_is_deterministic():
@@ -275,3 +290,32 @@ def test_pcg_one_step_full_size_c2():
     assert_rel(host(xs), x1, TOL)
     assert_rel(host(rs), r1, TOL)
     assert abs(host(scal)[nbx.S_RHO] - rho1) <= TOL * abs(rho1)
+
+
+@pytest.mark.parametrize("N,E", [(4, 37), (8, 9), (10, 131), (12, 5), (16, 3)])
+def test_every_tile_is_bit_identical(N, E):
+    """The autotuner's search space: every elements-per-workgroup choice
+    that fits computes the same bits (including the ragged last block)."""
+    u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(S.random_factors(E, N, seed=32))
+    D = nbx.deriv_device(N)
+    ref = None
+    for epb in (1, 2, 4):
+        try:
+            w = host(nbx.ax(u, G, D, epb=epb))
+        except nbx.NbxError as e:
+            assert e.status == -2   # tile does not fit in LDS
+            continue
+        if ref is None:
+            ref = w
+            assert_rel(w, O.ax(host(u), host(G), O.deriv(N)), TOL)
+        else:
+            assert np.array_equal(w, ref), epb
+
+
+def test_tile_table_roundtrip():
+    old = nbx.get_tile(nbx.F64, 10)
+    nbx.set_tile(nbx.F64, 10, 4)
+    assert nbx.get_tile(nbx.F64, 10) == 4
+    nbx.set_tile(nbx.F64, 10, old)
+    with pytest.raises(nbx.NbxError):
+        nbx.set_tile(nbx.F64, 10, 3)
