@@ -194,23 +194,26 @@ def main():
             _, r100 = st.problem.pcg(st.b, max_iter=100, fixed_iters=1, check_every=20)
             pcg["fp64_100_iterations_seconds"] = round(r100.seconds, 5)
             pcg["ms_per_iteration"] = round(r100.seconds / 100 * 1e3, 4)
-            try:
-                times = []
-                for _ in range(3):
-                    h0 = time.perf_counter()
-                    xm, rm = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32,
-                                            inner_rtol=1e-5, check_every=20)
-                    times.append(time.perf_counter() - h0)
-                err = float((xm - x64).abs().max() / x64.abs().max())
-                pcg["mixed_fp32"] = {"iters": rm.iters, "outer": rm.outer_iters,
-                                     "seconds": round(min(times), 5),
-                                     "true_relres": rm.true_relres,
-                                     "err_vs_fp64": err, "status": rm.status,
-                                     "speedup_vs_fp64": round(pcg["fp64"]["seconds"] /
-                                                              min(times), 3)}
-                log(f"mixed: {rm.iters} it / {rm.outer_iters} outer, {min(times):.4f} s")
-            except nbx.NbxError as e:
-                pcg["mixed_fp32"] = {"unavailable": str(e)}
+            variants = {"mixed_fp32": dict(mixed_mode=0, inner_rtol=0.1),
+                        "mixed_fp32_restarted": dict(mixed_mode=1, inner_rtol=1e-5)}
+            for name, kw in variants.items():
+                try:
+                    times = []
+                    for _ in range(3):
+                        h0 = time.perf_counter()
+                        xm, rm = st.problem.pcg(st.b, rtol=1e-10, max_iter=10000,
+                                                prec=nbx.F32, check_every=20, **kw)
+                        times.append(time.perf_counter() - h0)
+                    err = float((xm - x64).abs().max() / x64.abs().max())
+                    pcg[name] = {"iters": rm.iters, "outer": rm.outer_iters,
+                                 "seconds": round(min(times), 5),
+                                 "true_relres": rm.true_relres, "fell_back": rm.fell_back,
+                                 "err_vs_fp64": err, "status": rm.status,
+                                 "speedup_vs_fp64": round(pcg["fp64"]["seconds"] / min(times),
+                                                          3), **kw}
+                    log(f"{name}: {rm.iters} it / {rm.outer_iters} outer, {min(times):.4f} s")
+                except nbx.NbxError as e:
+                    pcg[name] = {"unavailable": str(e)}
             out["pcg"] = pcg
             del st, x, x64
             torch.cuda.empty_cache()

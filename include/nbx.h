@@ -206,10 +206,14 @@ typedef struct {
     int check_every;     /* iterations per graph launch between host checks */
     int use_graph;       /* nonzero: replay iterations from a captured hipGraph */
     double rtol;         /* stop when ||r||_c <= rtol ||b||_c */
-    int prec;            /* NBX_F64: plain FP64 PCG; NBX_F32: FP32 inner PCG in
-                            FP64 iterative refinement */
-    double inner_rtol;   /* inner relative tolerance for refinement */
-    int max_outer;       /* refinement cap */
+    int prec;            /* NBX_F64: plain FP64 PCG; NBX_F32: FP32 iteration
+                            with FP64 residuals (see mixed_mode) */
+    double inner_rtol;   /* mixed_mode 0: residual reduction per reliable
+                            update (e.g. 0.1); mixed_mode 1: relative
+                            tolerance of each inner solve (e.g. 1e-5) */
+    int max_outer;       /* cap on reliable updates / refinement steps */
+    int mixed_mode;      /* 0: one FP32 Krylov sequence with FP64 reliable
+                            updates; 1: restarted iterative refinement */
 } nbx_pcg_opts;
 
 typedef struct {

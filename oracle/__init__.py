@@ -67,6 +67,9 @@ def lib():
     L.ora_pcg.restype = C.c_int
     L.ora_num_threads.restype = C.c_int
     L.ora_set_num_threads.argtypes = [C.c_int]
+    _f = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+    L.ora_ax_f32.argtypes = [C.c_int, C.c_int64, _f, _f, _d, _f]
+    L.ora_dssum_f32.argtypes = [C.c_void_p, _f]
     _LIB = L
     return L
 
@@ -304,6 +307,85 @@ def ax_flops(N: int, E: int) -> int:
     pinned by the paper's 203 flops per point and 831488 per element at
     16 nodes per direction (Section II-B, Section III)."""
     return E * N ** 3 * (12 * N + 11)
+
+
+def ax_f32(u, G, D):
+    """AX in IEEE single arithmetic (u, G rounded to float, D rounded to
+    float inside).  Pinned against the FP64 AX at single-precision accuracy."""
+    D = _c(D); N = D.shape[0]; N3 = N ** 3
+    u = np.ascontiguousarray(u, dtype=np.float32).reshape(-1)
+    E = u.size // N3
+    w = np.zeros(E * N3, dtype=np.float32)
+    lib().ora_ax_f32(N, E, u, np.ascontiguousarray(G, dtype=np.float32).reshape(-1), D, w)
+    return w.reshape(E, N3)
+
+
+def dssum_f32(gs: GS, v):
+    v = np.array(v, dtype=np.float32, copy=True).reshape(-1)
+    lib().ora_dssum_f32(gs._h, v)
+    return v
+
+
+@dataclass
+class IRResult:
+    x: np.ndarray
+    outer: int
+    inner_iters: int
+    relres: float
+
+
+def _pcg32(P: Problem, G32, dinv32, r64, inner_rtol, max_iter):
+    """Jacobi-PCG on A d = r in single precision: float vectors, float AX
+    and dssum, dot products accumulated in double, alpha and beta in double
+    applied as floats.  Same step order as ora_pcg_iterate."""
+    c = P.c
+    bnd = P.bnd.astype(bool)
+    r = r64.astype(np.float32)
+    d = np.zeros_like(r)
+    z = dinv32 * r
+    p = z.copy()
+    rho = float(np.sum(c * r.astype(np.float64) * z.astype(np.float64)))
+    stop = inner_rtol ** 2 * float(np.sum(c * r.astype(np.float64) ** 2))
+    for k in range(max_iter):
+        w = dssum_f32(P.gs, ax_f32(p, G32, P.D).reshape(-1))
+        w[bnd] = 0.0
+        pap = float(np.sum(p.astype(np.float64) * w.astype(np.float64) * c))
+        alpha = rho / pap
+        d += np.float32(alpha) * p
+        r -= np.float32(alpha) * w
+        rr = float(np.sum(c * r.astype(np.float64) ** 2))
+        if rr <= stop:
+            return d, k + 1
+        z = dinv32 * r
+        rho2 = float(np.sum(c * r.astype(np.float64) * z.astype(np.float64)))
+        beta = rho2 / rho
+        rho = rho2
+        p = z + np.float32(beta) * p
+    return d, max_iter
+
+
+def ir_solve(P: Problem, b=None, rtol=1e-10, inner_rtol=1e-5, max_outer=20,
+             max_inner=5000) -> IRResult:
+    """Iterative refinement (Wilkinson; Moler 1967; Carson & Higham 2018):
+    x = 0, r = b; repeat: solve A d = r in single precision to inner_rtol,
+    x += d, r = b - A x in double, until ||r||_c <= rtol ||b||_c."""
+    b = P.b if b is None else _c(b).reshape(-1)
+    G32 = P.G.astype(np.float32)
+    dinv32 = P.dinv.astype(np.float32)
+    x = np.zeros(P.n)
+    r = b.copy()
+    bb = wdot(P.c, b, b)
+    total = 0
+    rel = np.sqrt(wdot(P.c, r, r) / bb) if bb > 0 else 0.0
+    outer = 0
+    while rel > rtol and outer < max_outer:
+        d, it = _pcg32(P, G32, dinv32, r, inner_rtol, max_inner)
+        total += it
+        outer += 1
+        x += d.astype(np.float64)
+        r = b - P.apply_A(x)
+        rel = np.sqrt(wdot(P.c, r, r) / bb)
+    return IRResult(x, outer, total, float(rel))
 
 
 def num_threads() -> int:

@@ -534,3 +534,79 @@ void ora_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------- single precision --
+ * The same operator and exchange in IEEE single arithmetic, for the
+ * iterative-refinement oracle (reduced precision is the paper's stated
+ * further work, Section V).  Identical steps to the double versions above:
+ * mxm with ascending inner sums, local_grad3, the geometric contraction,
+ * local_grad3_t with its two accumulations. */
+
+static void mxm_f(const float *A, int n1, const float *B, int n2, float *C, int n3)
+{
+    for (int j = 0; j < n3; ++j)
+        for (int i = 0; i < n1; ++i) {
+            float s = 0.0f;
+            for (int k = 0; k < n2; ++k) s += A[i + n1 * k] * B[k + n2 * j];
+            C[i + n1 * j] = s;
+        }
+}
+
+static void ax_e_f(float *w, const float *u, const float *g, int64_t N3, int N,
+                   const float *dxm1, const float *dxtm1, float *work)
+{
+    int N2 = N * N;
+    float *ur = work, *us = work + N3, *ut = work + 2 * N3, *tmp = work + 3 * N3;
+    mxm_f(dxm1, N, u, N, ur, N2);
+    for (int k = 0; k < N; ++k) mxm_f(u + k * N2, N, dxtm1, N, us + k * N2, N);
+    mxm_f(u, N2, dxtm1, N, ut, N);
+    for (int64_t i = 0; i < N3; ++i) {
+        float g1 = g[i], g2 = g[N3 + i], g3 = g[2 * N3 + i];
+        float g4 = g[3 * N3 + i], g5 = g[4 * N3 + i], g6 = g[5 * N3 + i];
+        float wr = g1 * ur[i] + g2 * us[i] + g3 * ut[i];
+        float ws = g2 * ur[i] + g4 * us[i] + g5 * ut[i];
+        float wt = g3 * ur[i] + g5 * us[i] + g6 * ut[i];
+        ur[i] = wr; us[i] = ws; ut[i] = wt;
+    }
+    mxm_f(dxtm1, N, ur, N, w, N2);
+    for (int k = 0; k < N; ++k) {
+        mxm_f(us + k * N2, N, dxm1, N, tmp, N);
+        for (int q = 0; q < N2; ++q) w[k * N2 + q] += tmp[q];
+    }
+    mxm_f(ut, N2, dxm1, N, tmp, N);
+    for (int64_t q = 0; q < N3; ++q) w[q] += tmp[q];
+}
+
+/* w = AX(u) in single precision; D is the double matrix rounded to float. */
+void ora_ax_f32(int N, int64_t E, const float *u, const float *G, const double *D, float *w)
+{
+    int64_t N3 = (int64_t)N * N * N;
+    float *dxm1 = (float *)malloc(sizeof(float) * N * N);
+    float *dxtm1 = (float *)malloc(sizeof(float) * N * N);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            dxm1[a + N * b] = (float)D[a * N + b];
+            dxtm1[b + N * a] = (float)D[a * N + b];
+        }
+    #pragma omp parallel
+    {
+        float *work = (float *)malloc(sizeof(float) * 4 * N3);
+        #pragma omp for schedule(static)
+        for (int64_t e = 0; e < E; ++e)
+            ax_e_f(w + e * N3, u + e * N3, G + e * 6 * N3, N3, N, dxm1, dxtm1, work);
+        free(work);
+    }
+    free(dxm1); free(dxtm1);
+}
+
+/* dssum in single precision, ascending local index. */
+void ora_dssum_f32(const ora_gs *gs, float *v)
+{
+    for (int64_t g = 0; g < gs->n_groups; ++g) {
+        int64_t b = gs->off[g], e = gs->off[g + 1];
+        if (e - b < 2) continue;
+        float s = 0.0f;
+        for (int64_t q = b; q < e; ++q) s += v[gs->idx[q]];
+        for (int64_t q = b; q < e; ++q) v[gs->idx[q]] = s;
+    }
+}

@@ -39,7 +39,8 @@ _lib = None
 class PcgOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
                 ("use_graph", C.c_int), ("rtol", C.c_double), ("prec", C.c_int),
-                ("inner_rtol", C.c_double), ("max_outer", C.c_int)]
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int),
+                ("mixed_mode", C.c_int)]
 
 
 class PcgResult(C.Structure):

@@ -1,0 +1,42 @@
+// solver.hpp -- the solver handle shared by the FP64 PCG driver (pcg.hip)
+// and the mixed-precision refinement driver (mixed.hip).
+#pragma once
+
+#include "internal.hpp"
+
+struct nbx_problem {
+    const double *G = nullptr, *D = nullptr;
+    int N = 0;
+    int64_t E = 0, n = 0;
+    nbx_gs *gs = nullptr;
+    // FP64 workspace
+    double *dinv = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
+    double *part1 = nullptr, *part3 = nullptr, *scal = nullptr, *tmp2 = nullptr;
+    double *h_scal = nullptr;   // pinned host mirror of a scalar block
+    hipStream_t ws = nullptr;   // the problem's own stream (default priority)
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t gexec = nullptr;   // FP64 iterations, captured per (x, chunk)
+    const double *g_x = nullptr;
+    int g_iters = 0;
+    // FP32 inner-solve workspace (allocated by the first mixed solve)
+    float *G32 = nullptr, *dinv32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr,
+          *w32 = nullptr, *d32 = nullptr;
+    double *scal32 = nullptr;
+    hipGraphExec_t gexec32 = nullptr;
+    int g32_iters = 0;
+};
+
+namespace nbx {
+
+// FP64 residual r = b - mask(dssum(AX(x))) (r may be null) and
+// out[0] = <r,r>_c, out[1] = <b,b>_c; synchronous on s.
+int residual_f64(nbx_problem *P, const double *b, const double *x, double *r, double out[2],
+                 hipStream_t s);
+
+int pcg_f64(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+            nbx_pcg_result *res);
+int pcg_mixed(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+              nbx_pcg_result *res);
+int prepare_f32(nbx_problem *P, hipStream_t s);
+
+}  // namespace nbx

@@ -1,0 +1,247 @@
+// solver_kernels.hpp -- vector updates and deterministic reductions of the
+// CG iteration (Section II-B: vector operations and global reductions),
+// templated on the vector type (FP64 solve, FP32 inner solve).  Scalars and
+// all dot products stay in FP64; partial sums are combined in a fixed
+// order, so reruns are bitwise identical.
+#pragma once
+
+#include "internal.hpp"
+
+namespace nbx {
+namespace sk {
+namespace {   // internal linkage: each solver translation unit has its own copy
+
+constexpr int kRedThreads = 256;
+constexpr int kMaxRedBlocks = 4096;
+constexpr double kFlagLimit = 3.0;
+
+__device__ inline double wsum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Two sums over a kRedThreads block, fixed order; valid in thread 0.
+__device__ inline void block_sum2(double &a, double &b)
+{
+    __shared__ double s[2][kRedThreads / 64];
+    a = wsum(a); b = wsum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { s[0][wid] = a; s[1][wid] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0, y = 0;
+        for (int q = 0; q < kRedThreads / 64; ++q) { x += s[0][q]; y += s[1][q]; }
+        a = x; b = y;
+    }
+}
+
+__device__ inline double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Per-node weight 1/multiplicity (info bits 0..6).
+__device__ inline double cw(uint8_t info) { return 1.0 / (double)(info & 0x7f); }
+
+inline int red_blocks(int64_t n)
+{
+    int64_t b = (n + 2 * kRedThreads - 1) / (2 * kRedThreads);
+    if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+    return (int)(b < 1 ? 1 : b);
+}
+
+// Start of a solve from x = 0 with right-hand side b (type TB, converted to
+// T): x = 0, r = b, z = dinv r, p = 0; partials of c r r and c r z.
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kRedThreads)
+init_kernel(int64_t n, const TB *__restrict__ b, const T *__restrict__ dinv,
+            const uint8_t *__restrict__ info, T *__restrict__ x, T *__restrict__ r,
+            T *__restrict__ z, T *__restrict__ p, double *__restrict__ part)
+{
+    double rr = 0, rz = 0;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const T rv = (T)b[l], zv = dinv[l] * rv;
+        const double c = cw(info[l]);
+        x[l] = 0; r[l] = rv; z[l] = zv; p[l] = 0;
+        rr += c * (double)rv * (double)rv;
+        rz += c * (double)rv * (double)zv;
+    }
+    block_sum2(rr, rz);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = rz; }
+}
+
+// scal <- fresh state: RR = BB = sum of the first partials, RHO = second,
+// STOP = rtol^2 BB (or -1), MAXIT, FLAG (converged at once if BB == 0).
+__global__ void __launch_bounds__(1024)
+init_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal,
+                   double rtol, int fixed, int max_iter)
+{
+    __shared__ double s[2][16];
+    double a = 0, b = 0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    a = wsum(a); b = wsum(b);
+    if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bb = 0, rho = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { bb += s[0][q]; rho += s[1][q]; }
+        for (int q = 0; q < NBX_SCAL_LEN; ++q) scal[q] = 0.0;
+        scal[NBX_S_BB] = bb;
+        scal[NBX_S_RHO] = rho;
+        scal[NBX_S_RR] = bb;
+        scal[NBX_S_STOP] = fixed ? -1.0 : rtol * rtol * bb;
+        scal[NBX_S_MAXIT] = (double)max_iter;
+        scal[NBX_S_FLAG] = (bb == 0.0) ? 1.0 : (max_iter <= 0 ? kFlagLimit : 0.0);
+    }
+}
+
+// R1: pap from the AX partials; alpha; breakdown check.
+__global__ void __launch_bounds__(1024)
+pap_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+{
+    if (scal[NBX_S_FLAG] != 0.0) return;
+    __shared__ double s[16];
+    double a = 0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) a += part[q];
+    a = wsum(a);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double pap = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) pap += s[q];
+        scal[NBX_S_PAP] = pap;
+        if (!(pap > 0.0) || !isfinite(pap)) scal[NBX_S_FLAG] = 2.0;
+        else scal[NBX_S_ALPHA] = scal[NBX_S_RHO] / pap;
+    }
+}
+
+template <typename T> struct Vec;
+template <> struct Vec<double> {
+    typedef double v __attribute__((ext_vector_type(2)));
+    typedef uint16_t iv;
+    static constexpr int W = 2;
+};
+template <> struct Vec<float> {
+    typedef float v __attribute__((ext_vector_type(4)));
+    typedef uint32_t iv;
+    static constexpr int W = 4;
+};
+
+// K3: x += alpha p; r -= alpha w; z = dinv r; partials of c r r and c r z.
+// Vector accesses of 16 bytes per lane, scalar tail.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
+              const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
+              T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
+              const double *__restrict__ scal)
+{
+    if (scal[NBX_S_FLAG] != 0.0) return;
+    using V = Vec<T>;
+    constexpr int W = V::W;
+    const T alpha = (T)scal[NBX_S_ALPHA];
+    double rr = 0, rz = 0;
+    const int64_t nv = n / W;
+    const typename V::v *pv = reinterpret_cast<const typename V::v *>(p);
+    const typename V::v *wv = reinterpret_cast<const typename V::v *>(w);
+    const typename V::v *dv = reinterpret_cast<const typename V::v *>(dinv);
+    typename V::v *xv = reinterpret_cast<typename V::v *>(x);
+    typename V::v *rv = reinterpret_cast<typename V::v *>(r);
+    typename V::v *zv = reinterpret_cast<typename V::v *>(z);
+    const typename V::iv *iv = reinterpret_cast<const typename V::iv *>(info);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const typename V::v pq = pv[q], wq = wv[q], dq = dv[q];
+        typename V::v xq = xv[q], rq = rv[q], zq;
+        const typename V::iv inf = iv[q];
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            xq[c] = fmaT(alpha, pq[c], xq[c]);
+            rq[c] = fmaT(-alpha, wq[c], rq[c]);
+            zq[c] = dq[c] * rq[c];
+            const double cc = cw((uint8_t)(inf >> (8 * c)));
+            rr += cc * (double)rq[c] * (double)rq[c];
+            rz += cc * (double)rq[c] * (double)zq[c];
+        }
+        xv[q] = xq; rv[q] = rq; zv[q] = zq;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int64_t l = nv * W; l < n; ++l) {
+            x[l] = fmaT(alpha, p[l], x[l]);
+            const T rl = fmaT(-alpha, w[l], r[l]), zl = dinv[l] * rl;
+            const double cc = cw(info[l]);
+            r[l] = rl; z[l] = zl;
+            rr += cc * (double)rl * (double)rl;
+            rz += cc * (double)rl * (double)zl;
+        }
+    }
+    block_sum2(rr, rz);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = rz; }
+}
+
+// R3: rr, rho'; convergence / breakdown / iteration limit; beta.
+__global__ void __launch_bounds__(1024)
+rr_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+{
+    if (scal[NBX_S_FLAG] != 0.0) return;
+    __shared__ double s[2][16];
+    double a = 0, b = 0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    a = wsum(a); b = wsum(b);
+    if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rr = 0, rz = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { rr += s[0][q]; rz += s[1][q]; }
+        const double it = scal[NBX_S_ITER] + 1.0;
+        scal[NBX_S_ITER] = it;
+        scal[NBX_S_RR] = rr;
+        if (rr <= scal[NBX_S_STOP]) {
+            scal[NBX_S_FLAG] = 1.0;
+        } else if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+            scal[NBX_S_FLAG] = 2.0;
+        } else {
+            scal[NBX_S_BETA] = rz / scal[NBX_S_RHO];
+            scal[NBX_S_RHO] = rz;
+            if (it >= scal[NBX_S_MAXIT]) scal[NBX_S_FLAG] = kFlagLimit;
+        }
+    }
+}
+
+// Partials of c (b - w)^2 and c b^2 (FP64 residual of a refinement step);
+// optionally stores r = b - w.
+__global__ void __launch_bounds__(kRedThreads)
+resid_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ w,
+             const uint8_t *__restrict__ info, double *__restrict__ r, double *__restrict__ part)
+{
+    double a = 0, c2 = 0;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const double c = cw(info[l]), d = b[l] - w[l];
+        if (r) r[l] = d;
+        a += c * d * d; c2 += c * b[l] * b[l];
+    }
+    block_sum2(a, c2);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = c2; }
+}
+
+__global__ void __launch_bounds__(1024)
+sum2_kernel(int nb, const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double s[2][16];
+    double a = 0, b = 0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    a = wsum(a); b = wsum(b);
+    if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0, y = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { x += s[0][q]; y += s[1][q]; }
+        out[0] = x; out[1] = y;
+    }
+}
+
+}  // namespace
+}  // namespace sk
+}  // namespace nbx

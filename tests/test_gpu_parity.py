@@ -319,3 +319,54 @@ def test_tile_table_roundtrip():
     nbx.set_tile(nbx.F64, 10, old)
     with pytest.raises(nbx.NbxError):
         nbx.set_tile(nbx.F64, 10, 3)
+
+
+# ---------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("N", [6, 10])
+def test_ax_fp32_matches_oracle_fp32(N):
+    E = 33
+    u = S.uniform_field(E, N, seed=41).astype(np.float32)
+    G = S.random_factors(E, N, seed=42).astype(np.float32)
+    want = O.ax_f32(u, G, O.deriv(N))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
+    assert_rel(got, want, 16 * N * np.finfo(np.float32).eps)
+
+
+@pytest.mark.parametrize("case,mode", [("deformed8", 0), ("c1", 0), ("deformed8", 1), ("c1", 1)])
+def test_mixed_precision_solve(case, mode):
+    """mode 0: one FP32 Krylov sequence with FP64 reliable updates every
+    tenfold residual drop; mode 1: restarted refinement, inner solves to
+    1e-5.  Either way the FP64 true residual must reach 1e-10."""
+    b = S.scaled_c2_brick(4, 8) if case == "deformed8" else S.c1_brick()
+    P = O.setup(b)
+    ref = O.pcg(P, max_iter=5000, rtol=1e-13)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32,
+                            inner_rtol=0.1 if mode == 0 else 1e-5, mixed_mode=mode)
+    print(f"mixed {case} mode {mode}: {res.iters} it, {res.outer_iters} outer, "
+          f"relres {res.relres:.2e} (fp64 oracle {ref.iters} it)")
+    assert res.status == 0 and res.flag == 1 and res.fell_back == 0
+    if mode == 1:
+        assert 2 <= res.outer_iters <= 5
+    else:
+        assert 5 <= res.outer_iters <= 30
+    xh = host(x).reshape(-1)
+    true = P.b - P.apply_A(xh)          # the oracle's own FP64 operator
+    assert np.sqrt(O.wdot(P.c, true, true) / O.wdot(P.c, P.b, P.b)) <= 2e-10
+    assert_rel(xh, ref.x, 1e-8)
+
+
+def test_mixed_precision_falls_back_when_refinement_stalls():
+    """An inner tolerance of 0.5 cannot give the tenfold reduction per outer
+    step the driver demands, so it must finish with FP64 PCG."""
+    b = S.scaled_c2_brick(3, 6)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32, inner_rtol=0.5,
+                            mixed_mode=1)
+    assert res.fell_back == 1 and res.status == 0 and res.relres <= 1e-10
+    # reliable updates every 1% of reduction cannot show the fourfold drop
+    # per update the stall detector demands
+    x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32, inner_rtol=0.99,
+                            mixed_mode=0)
+    assert res.fell_back == 1 and res.status == 0 and res.relres <= 1e-10
