@@ -150,11 +150,17 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
     typename V::v *rv = reinterpret_cast<typename V::v *>(r);
     typename V::v *zv = reinterpret_cast<typename V::v *>(z);
     const typename V::iv *iv = reinterpret_cast<const typename V::iv *>(info);
+    // every array is streamed once per iteration (and exceeds the caches at
+    // benchmark sizes): non-temporal loads and stores throughout
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const typename V::v pq = pv[q], wq = wv[q], dq = dv[q];
-        typename V::v xq = xv[q], rq = rv[q], zq;
-        const typename V::iv inf = iv[q];
+        const typename V::v pq = __builtin_nontemporal_load(pv + q);
+        const typename V::v wq = __builtin_nontemporal_load(wv + q);
+        const typename V::v dq = __builtin_nontemporal_load(dv + q);
+        typename V::v xq = __builtin_nontemporal_load(xv + q);
+        typename V::v rq = __builtin_nontemporal_load(rv + q);
+        typename V::v zq;
+        const typename V::iv inf = __builtin_nontemporal_load(iv + q);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             xq[c] = fmaT(alpha, pq[c], xq[c]);
@@ -164,7 +170,9 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
             rr += cc * (double)rq[c] * (double)rq[c];
             rz += cc * (double)rq[c] * (double)zq[c];
         }
-        xv[q] = xq; rv[q] = rq; zv[q] = zq;
+        __builtin_nontemporal_store(xq, xv + q);
+        __builtin_nontemporal_store(rq, rv + q);
+        __builtin_nontemporal_store(zq, zv + q);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         for (int64_t l = nv * W; l < n; ++l) {
