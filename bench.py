@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n", type=int, default=32, help="elements per brick edge")
     ap.add_argument("--N", type=int, default=10, help="GLL nodes per direction")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-solve leg")
+    ap.add_argument("--nbatch", type=int, default=64, help="problems in the batched leg")
     return ap.parse_args()
 
 
@@ -220,6 +222,47 @@ def main():
                     pcg[name] = {"unavailable": str(e)}
             out["pcg"] = pcg
             del st, x, x64
+            torch.cuda.empty_cache()
+
+    # ---- batched solves: independent problems of uneven E and N together
+    if not a.no_batched:
+        with torch.cuda.stream(stream):
+            log(f"batched set-up: {a.nbatch} problems")
+            specs = S.c4_problems(a.nbatch)
+            sets = [nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array(),
+                                    f=torch.as_tensor(S.rhs_values(b)).to(dev)) for b in specs]
+            stream.synchronize()
+            probs = [s_.problem for s_ in sets]
+            bs = [s_.b for s_ in sets]
+            nbx.pcg_batched(probs, bs, rtol=1e-10, max_iter=5000, check_every=20)
+            h0 = time.perf_counter()
+            xs, res, lat = nbx.pcg_batched(probs, bs, rtol=1e-10, max_iter=5000, check_every=20)
+            wall = time.perf_counter() - h0
+            # the same problems one after another with the standalone solver
+            h1 = time.perf_counter()
+            seq_iters = []
+            for s_ in sets:
+                _, r1 = s_.problem.pcg(s_.b, rtol=1e-10, max_iter=5000, check_every=20)
+                seq_iters.append(r1.iters)
+            seq = time.perf_counter() - h1
+            flops = sum(r.iters * nbx.ax_flops(b.N, b.E) for r, b in zip(res, specs))
+            lat_sorted = sorted(lat)
+            pct = lambda q: lat_sorted[min(len(lat_sorted) - 1, int(q * len(lat_sorted)))]
+            out["batched"] = {
+                "problems": len(specs), "nodes": int(sum(b.n_local for b in specs)),
+                "converged": int(sum(r.flag == 1 for r in res)),
+                "same_iterations_as_standalone": bool(all(r.iters == i for r, i
+                                                          in zip(res, seq_iters))),
+                "wall_seconds": round(wall, 4), "sequential_seconds": round(seq, 4),
+                "speedup_vs_sequential": round(seq / wall, 3),
+                "ax_gflops_aggregate": round(flops / wall / 1e9, 1),
+                "latency_p50_s": round(pct(0.50), 5), "latency_p99_s": round(pct(0.99), 5),
+                "latency_max_s": round(lat_sorted[-1], 5),
+                "iterations_min_max": [min(r.iters for r in res), max(r.iters for r in res)],
+                "tiles": {str(N): nbx.get_tile(nbx.F64, N) for N in (6, 8, 10, 12)}}
+            log(f"batched: {wall:.3f} s vs sequential {seq:.3f} s, "
+                f"p50 {pct(0.5):.4f} s p99 {pct(0.99):.4f} s")
+            del sets, probs, bs, xs
             torch.cuda.empty_cache()
 
     # ---- CPU oracle baseline (host cores, bounded sample)

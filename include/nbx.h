@@ -235,6 +235,22 @@ void nbx_pcg_default_opts(nbx_pcg_opts *opts);
 int nbx_pcg(nbx_problem *p, const double *b, double *x, const nbx_pcg_opts *opts,
             nbx_pcg_result *res, void *stream);
 
+/* Solves nprob independent problems (each with its own N, E, G, plan and
+ * workspace) together: every fused step of the FP64 Jacobi-PCG iteration is
+ * one launch serving all unconverged problems, replayed from a captured
+ * hipGraph of check_every iterations (the elements of independent problems
+ * are independent work, as the paper distributes independent elements over
+ * kernels, Section IV).  probs, b and x are host arrays of nprob handles /
+ * device pointers; results[nprob] is filled per problem (seconds = the whole
+ * batch); solve_seconds[nprob] (may be NULL) receives each problem's time
+ * from the batch start to its convergence on the device clock.  Results are
+ * bit-identical to nbx_pcg on each problem alone.  Synchronous.  Only
+ * opts->prec == NBX_F64.  Returns NBX_OK if every problem converged, else
+ * NBX_NOT_CONVERGED or NBX_EBREAKDOWN.  A problem must not appear twice. */
+int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b, double *const *x,
+                    int nprob, const nbx_pcg_opts *opts, nbx_pcg_result *results,
+                    double *solve_seconds, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

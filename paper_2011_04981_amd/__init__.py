@@ -86,13 +86,33 @@ def lib():
         "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "nbx_pcg_default_opts": ([C.POINTER(PcgOpts)], None),
         "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
+        "nbx_pcg_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32,
+                             C.POINTER(PcgOpts), C.POINTER(PcgResult), C.POINTER(dp), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
     _lib = L
+    _apply_tile_cache(L)
     return L
+
+
+def _apply_tile_cache(L) -> None:
+    """Installs the autotuner's stored tiles (tiles.json next to this file, or
+    $NBX_TILE_CACHE) into the library's tile table."""
+    import json
+    path = os.environ.get("NBX_TILE_CACHE", os.path.join(HERE, "tiles.json"))
+    if not os.path.exists(path):
+        return
+    with open(path) as f:
+        rec = json.load(f)
+    for pname, rows in rec.get("tiles", {}).items():
+        prec = {"f64": F64, "f32": F32}.get(pname)
+        if prec is None:
+            continue
+        for N, row in rows.items():
+            L.nbx_ax_set_tile(prec, int(N), int(row["epb"]))
 
 
 def _check(st: int, what: str) -> int:
@@ -413,3 +433,25 @@ def setup_brick(ex: int, ey: int, ez: int, N: int, deform=None, f=None, device="
         f = sine_source(xyz, stream=stream)
     b = rhs(gs, bm, f, stream=stream)
     return BrickSetup(N, ex * ey * ez, D, G, bm, xyz, gs, P, b)
+
+
+def pcg_batched(problems, bs, xs=None, stream=None, **opts):
+    """Solves independent problems together (nbx_pcg_batched).  Returns
+    (xs, [SolveResult], per-solve seconds on the device clock)."""
+    torch = _torch()
+    n = len(problems)
+    if len(bs) != n:
+        raise ValueError("one right-hand side per problem")
+    xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+    P_arr = (C.c_void_p * n)(*[p._h.value for p in problems])
+    b_arr = (C.c_void_p * n)(*[_dptr(b, torch.float64, "b").value for b in bs])
+    x_arr = (C.c_void_p * n)(*[_dptr(x, torch.float64, "x").value for x in xs])
+    res = (PcgResult * n)()
+    lat = (C.c_double * n)()
+    o = default_opts(**opts)
+    st = lib().nbx_pcg_batched(P_arr, b_arr, x_arr, n, C.byref(o), res, lat, _stream(stream))
+    if st < 0 and st != -5:
+        raise NbxError(st, "nbx_pcg_batched")
+    out = [SolveResult(st, r.iters, r.outer_iters, r.relres, r.true_relres, r.fell_back,
+                       r.flag, r.seconds) for r in res]
+    return xs, out, list(lat)

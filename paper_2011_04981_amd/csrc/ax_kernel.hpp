@@ -69,11 +69,14 @@ __device__ inline float ax_fma(float a, float b, float c) { return __builtin_fma
 // PCG == true : uin is z; p <- z + beta p (stored); w = AX(p);
 //               part[block] = sum over the block's elements of p*w
 //               (skipped entirely once scal[FLAG] != 0).
+// blk selects the block's elements [blk*EPB, blk*EPB + EPB) of this
+// operator instance (blockIdx.x for a single operator; a table entry when
+// one launch serves several independent problems).
 template <typename T, int N, int EPB, bool PCG>
-__global__ void __launch_bounds__((AxShape<N, EPB>::NT))
-ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
-          T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
-          const double *__restrict__ scal, int64_t E)
+__device__ __forceinline__ void
+ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
+        T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
+        const double *__restrict__ scal, int64_t E, int64_t blk)
 {
 #pragma clang fp contract(off)
     using S = AxShape<N, EPB>;
@@ -93,7 +96,7 @@ ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__re
     const int tl = lane_act ? t : NACT - 1;    // idle lanes shadow a real column
     const int el = tl / N2, tc = tl - el * N2;
     const int i = tc % N, j = tc / N;
-    const int64_t e_raw = (int64_t)blockIdx.x * EPB + el;
+    const int64_t e_raw = blk * EPB + el;
     const bool valid = lane_act && e_raw < E;  // ragged last block
     const int64_t e = e_raw < E ? e_raw : E - 1;
     const size_t base = (size_t)e * N3;
@@ -197,9 +200,18 @@ ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__re
             double s = 0.0;
 #pragma unroll
             for (int q = 0; q < NT / 64; ++q) s += s_red[q];
-            part[blockIdx.x] = s;
+            part[blk] = s;
         }
     }
+}
+
+template <typename T, int N, int EPB, bool PCG>
+__global__ void __launch_bounds__((AxShape<N, EPB>::NT))
+ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
+          T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
+          const double *__restrict__ scal, int64_t E)
+{
+    ax_body<T, N, EPB, PCG>(uin, G, Dg, w, pio, part, scal, E, (int64_t)blockIdx.x);
 }
 
 // Elements per workgroup the library may use (the autotuner's search space).

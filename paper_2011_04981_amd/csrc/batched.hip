@@ -1,0 +1,352 @@
+// batched.hip -- many independent Jacobi-PCG solves of uneven size and
+// polynomial order advanced together.
+//
+// Each problem keeps its own workspace (nbx_problem).  A device table of
+// per-problem descriptors plus, for every fused step of the iteration, a
+// table of (problem, block) entries lets ONE launch of that step serve every
+// problem: the AX step is launched once per polynomial size present (its
+// kernel is specialised on N, with the tile the autotuner chose), the
+// reductions once with one workgroup per problem, dssum and the vector
+// update once over all problems' blocks.  Blocks of a converged problem
+// return at once, so the batch shrinks as problems finish.  The host replays
+// a captured hipGraph of `check_every` iterations until every problem's
+// flag is set.  The per-problem arithmetic is exactly the standalone
+// solver's (same bodies, same block counts, same reduction order): batched
+// results are bit-identical to solving each problem alone.
+//
+// The paper distributes independent elements across kernels (Section IV);
+// here independent problems share launches for the same reason: the GPU is
+// only full when small problems are processed together.
+#include "solver.hpp"
+#include "solver_kernels.hpp"
+#include "ax_kernel.hpp"
+#include "gs_kernels.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+namespace nbx {
+namespace {
+
+struct BDesc {
+    const double *G, *D, *dinv, *b;
+    const uint8_t *info;
+    double *x, *r, *z, *p, *w, *part1, *part3, *scal, *stamp;
+    const int32_t *off, *idx, *mask_idx;
+    const uint8_t *gflag;
+    int32_t n_groups, n_mask_only;
+    int64_t E, n;
+    int32_t N, nb1, nb3, pad;
+};
+
+struct BEntry {
+    int32_t pid, blk;
+};
+
+__global__ void __launch_bounds__(sk::kRedThreads)
+b_init_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    sk::init_body<double, double>(d.n, d.b, d.dinv, d.info, d.x, d.r, d.z, d.p, d.part3, en.blk,
+                                  d.nb3);
+}
+
+__global__ void __launch_bounds__(1024)
+b_init_reduce_kernel(const BDesc *__restrict__ desc, double rtol, int fixed, int max_iter)
+{
+    const BDesc &d = desc[blockIdx.x];
+    sk::init_reduce_body(d.nb3, d.part3, d.scal, rtol, fixed, max_iter);
+}
+
+template <int N, int EPB>
+__global__ void __launch_bounds__((AxShape<N, EPB>::NT))
+b_ax_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    ax_body<double, N, EPB, true>(d.z, d.G, d.D, d.w, d.p, d.part1, d.scal, d.E, en.blk);
+}
+
+__global__ void __launch_bounds__(1024) b_pap_kernel(const BDesc *__restrict__ desc)
+{
+    const BDesc &d = desc[blockIdx.x];
+    sk::pap_reduce_body(d.nb1, d.part1, d.scal);
+}
+
+__global__ void __launch_bounds__(256)
+b_dssum_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    if (d.scal[NBX_S_FLAG] != 0.0) return;
+    const int32_t g = en.blk * 256 + threadIdx.x;
+    if (g < d.n_groups) dssum_group<double>(g, d.off, d.idx, d.gflag, d.w, 1);
+}
+
+__global__ void __launch_bounds__(256)
+b_mask_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    if (d.scal[NBX_S_FLAG] != 0.0) return;
+    const int32_t q = en.blk * 256 + threadIdx.x;
+    if (q < d.n_mask_only) d.w[d.mask_idx[q]] = 0.0;
+}
+
+__global__ void __launch_bounds__(sk::kRedThreads)
+b_update_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    sk::update_body<double>(d.n, d.p, d.w, d.dinv, d.info, d.x, d.r, d.z, d.part3, d.scal,
+                            en.blk, d.nb3);
+}
+
+__global__ void __launch_bounds__(1024) b_rr_kernel(const BDesc *__restrict__ desc)
+{
+    const BDesc &d = desc[blockIdx.x];
+    sk::rr_reduce_body(d.nb3, d.part3, d.scal, d.stamp);
+}
+
+__global__ void b_clock_kernel(double *t0) { *t0 = (double)wall_clock64(); }
+
+template <int N>
+int launch_b_ax(int epb, const BDesc *desc, const BEntry *tab, int nblk, hipStream_t s)
+{
+    switch (epb) {
+#define NBX_BAX(EE)                                                                          \
+    case EE:                                                                                 \
+        if constexpr (AxShape<N, EE>::template fits<double>()) {                             \
+            hipLaunchKernelGGL((b_ax_kernel<N, EE>), dim3(nblk), dim3(AxShape<N, EE>::NT),   \
+                               0, s, desc, tab);                                             \
+            return NBX_OK;                                                                   \
+        } else {                                                                             \
+            return NBX_EUNSUPPORTED;                                                         \
+        }
+        NBX_BAX(1) NBX_BAX(2) NBX_BAX(4)
+#undef NBX_BAX
+        default: return NBX_EINVAL;
+    }
+}
+
+int launch_b_ax_n(int N, int epb, const BDesc *desc, const BEntry *tab, int nblk, hipStream_t s)
+{
+    switch (N) {
+#define NBX_BAXN(NN) case NN: return launch_b_ax<NN>(epb, desc, tab, nblk, s);
+        NBX_BAXN(2) NBX_BAXN(3) NBX_BAXN(4) NBX_BAXN(5) NBX_BAXN(6) NBX_BAXN(7) NBX_BAXN(8)
+        NBX_BAXN(9) NBX_BAXN(10) NBX_BAXN(11) NBX_BAXN(12) NBX_BAXN(13) NBX_BAXN(14)
+        NBX_BAXN(15) NBX_BAXN(16)
+#undef NBX_BAXN
+        default: return NBX_EINVAL;
+    }
+}
+
+// Device copies of the batch's tables, freed by the destructor.
+struct BatchPlan {
+    int nprob = 0;
+    BDesc *desc = nullptr;
+    double *stamps = nullptr, *t0 = nullptr;
+    BEntry *t_vec = nullptr, *t_gs = nullptr, *t_mask = nullptr;
+    int n_vec = 0, n_gs = 0, n_mask = 0;
+    struct AxClass { int N, epb, nblk; BEntry *tab; };
+    std::vector<AxClass> ax;
+    ~BatchPlan()
+    {
+        hipFree(desc); hipFree(stamps); hipFree(t0);
+        hipFree(t_vec); hipFree(t_gs); hipFree(t_mask);
+        for (auto &c : ax) hipFree(c.tab);
+    }
+};
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &h)
+{
+    if (hipMalloc(dst, std::max<size_t>(h.size(), 1) * sizeof(T)) != hipSuccess) return NBX_ENOMEM;
+    if (!h.empty())
+        NBX_HIP(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return NBX_OK;
+}
+
+int enqueue_batch_iters(const BatchPlan &B, int n_iter, hipStream_t s)
+{
+    for (int it = 0; it < n_iter; ++it) {
+        for (const auto &c : B.ax) {
+            int st = launch_b_ax_n(c.N, c.epb, B.desc, c.tab, c.nblk, s);
+            if (st != NBX_OK) return st;
+        }
+        hipLaunchKernelGGL(b_pap_kernel, dim3(B.nprob), dim3(1024), 0, s, B.desc);
+        if (B.n_gs > 0)
+            hipLaunchKernelGGL(b_dssum_kernel, dim3(B.n_gs), dim3(256), 0, s, B.desc, B.t_gs);
+        if (B.n_mask > 0)
+            hipLaunchKernelGGL(b_mask_kernel, dim3(B.n_mask), dim3(256), 0, s, B.desc, B.t_mask);
+        hipLaunchKernelGGL(b_update_kernel, dim3(B.n_vec), dim3(sk::kRedThreads), 0, s, B.desc,
+                           B.t_vec);
+        hipLaunchKernelGGL(b_rr_kernel, dim3(B.nprob), dim3(1024), 0, s, B.desc);
+        NBX_LAUNCH_CHECK();
+    }
+    return NBX_OK;
+}
+
+}  // namespace
+}  // namespace nbx
+
+using namespace nbx;
+
+extern "C" int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b,
+                               double *const *x, int nprob, const nbx_pcg_opts *opts,
+                               nbx_pcg_result *results, double *solve_seconds, void *stream)
+{
+    if (nprob < 0 || (nprob > 0 && (!probs || !b || !x || !results))) return NBX_EINVAL;
+    if (nprob == 0) return NBX_OK;
+    nbx_pcg_opts o;
+    if (opts) o = *opts; else nbx_pcg_default_opts(&o);
+    if (o.max_iter < 0 || !(o.rtol >= 0)) return NBX_EINVAL;
+    if (o.prec != NBX_F64) return NBX_EUNSUPPORTED;
+    for (int p = 0; p < nprob; ++p)
+        if (!probs[p] || !b[p] || !x[p]) return NBX_EINVAL;
+
+    BatchPlan B;
+    B.nprob = nprob;
+    std::vector<BDesc> hd(nprob);
+    std::vector<BEntry> tv, tg, tm;
+    for (int p = 0; p < nprob; ++p) {
+        nbx_problem *P = probs[p];
+        const GsPlan &g = P->gs->plan;
+        BDesc &d = hd[p];
+        d.G = P->G; d.D = P->D; d.dinv = P->dinv; d.b = b[p]; d.info = g.info;
+        d.x = x[p]; d.r = P->r; d.z = P->z; d.p = P->p; d.w = P->w;
+        d.part1 = P->part1; d.part3 = P->part3; d.scal = P->scal; d.stamp = nullptr;
+        d.off = g.off; d.idx = g.idx; d.mask_idx = g.mask_idx; d.gflag = g.gflag;
+        d.n_groups = g.n_groups; d.n_mask_only = g.n_mask_only;
+        d.E = P->E; d.n = P->n; d.N = P->N;
+        d.nb1 = ax_blocks(NBX_F64, P->N, P->E);
+        d.nb3 = sk::red_blocks(P->n);
+        d.pad = 0;
+        for (int q = 0; q < d.nb3; ++q) tv.push_back({p, q});
+        for (int q = 0; q < (g.n_groups + 255) / 256; ++q) tg.push_back({p, q});
+        for (int q = 0; q < (g.n_mask_only + 255) / 256; ++q) tm.push_back({p, q});
+    }
+    int st;
+    if (hipMalloc(&B.stamps, sizeof(double) * nprob) != hipSuccess ||
+        hipMalloc(&B.t0, sizeof(double)) != hipSuccess)
+        return NBX_ENOMEM;
+    NBX_HIP(hipMemset(B.stamps, 0, sizeof(double) * nprob));
+    for (int p = 0; p < nprob; ++p) hd[p].stamp = B.stamps + p;
+    if ((st = upload(&B.desc, hd)) != NBX_OK) return st;
+    if ((st = upload(&B.t_vec, tv)) != NBX_OK) return st;
+    if ((st = upload(&B.t_gs, tg)) != NBX_OK) return st;
+    if ((st = upload(&B.t_mask, tm)) != NBX_OK) return st;
+    B.n_vec = (int)tv.size(); B.n_gs = (int)tg.size(); B.n_mask = (int)tm.size();
+    // one AX table per polynomial size present, with that size's tile
+    std::vector<int> Ns;
+    for (int p = 0; p < nprob; ++p) Ns.push_back(probs[p]->N);
+    std::sort(Ns.begin(), Ns.end());
+    Ns.erase(std::unique(Ns.begin(), Ns.end()), Ns.end());
+    for (int N : Ns) {
+        std::vector<BEntry> ta;
+        for (int p = 0; p < nprob; ++p)
+            if (probs[p]->N == N)
+                for (int q = 0; q < hd[p].nb1; ++q) ta.push_back({p, q});
+        BatchPlan::AxClass c{N, ax_tile(NBX_F64, N), (int)ta.size(), nullptr};
+        if ((st = upload(&c.tab, ta)) != NBX_OK) return st;
+        B.ax.push_back(c);
+    }
+
+    hipStream_t cs = as_stream(stream);
+    hipStream_t s = nullptr;
+    NBX_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t ev = nullptr;
+    NBX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    double *h = nullptr;
+    NBX_HIP(hipHostMalloc(&h, sizeof(double) * NBX_SCAL_LEN * nprob, hipHostMallocDefault));
+    hipGraphExec_t gexec = nullptr;
+    auto cleanup = [&]() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (s) { hipStreamSynchronize(s); hipStreamDestroy(s); }
+        if (ev) hipEventDestroy(ev);
+        if (h) hipHostFree(h);
+    };
+    auto fail = [&](int code) { cleanup(); return code; };
+
+    if (hipEventRecord(ev, cs) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess)
+        return fail(NBX_EHIP);
+    const int chunk = o.check_every > 0 ? o.check_every : 10;
+    if (o.use_graph) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(NBX_EHIP);
+        st = enqueue_batch_iters(B, chunk, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != NBX_OK) { if (g) hipGraphDestroy(g); return fail(st); }
+        if (e != hipSuccess) return fail(hip_fail(e, "hipStreamEndCapture"));
+        e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) { gexec = nullptr; return fail(hip_fail(e, "hipGraphInstantiate")); }
+    }
+    int dev = 0, rate_khz = 0;
+    NBX_HIP(hipGetDevice(&dev));
+    NBX_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+
+    const auto t0 = std::chrono::steady_clock::now();
+    hipLaunchKernelGGL(b_init_kernel, dim3(B.n_vec), dim3(sk::kRedThreads), 0, s, B.desc, B.t_vec);
+    hipLaunchKernelGGL(b_init_reduce_kernel, dim3(nprob), dim3(1024), 0, s, B.desc, o.rtol,
+                       o.fixed_iters, o.max_iter);
+    hipLaunchKernelGGL(b_clock_kernel, dim3(1), dim3(1), 0, s, B.t0);
+    if (hipGetLastError() != hipSuccess) return fail(NBX_EHIP);
+    int done = 0;
+    std::vector<double> host_scal(NBX_SCAL_LEN);
+    while (true) {
+        if (o.use_graph) {
+            if (hipGraphLaunch(gexec, s) != hipSuccess) return fail(NBX_EHIP);
+        } else {
+            st = enqueue_batch_iters(B, chunk, s);
+            if (st != NBX_OK) return fail(st);
+        }
+        done += chunk;
+        bool all = true;
+        for (int p = 0; p < nprob; ++p)
+            if (hipMemcpyAsync(h + p * NBX_SCAL_LEN, probs[p]->scal, sizeof(double) * NBX_SCAL_LEN,
+                               hipMemcpyDeviceToHost, s) != hipSuccess)
+                return fail(NBX_EHIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(NBX_EHIP);
+        for (int p = 0; p < nprob; ++p)
+            if (h[p * NBX_SCAL_LEN + NBX_S_FLAG] == 0.0) { all = false; break; }
+        if (all || done >= o.max_iter + chunk) break;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    const double wall = std::chrono::duration<double>(t1 - t0).count();
+    std::vector<double> stamps(nprob);
+    double t0d = 0.0;
+    if (hipMemcpy(stamps.data(), B.stamps, sizeof(double) * nprob, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(&t0d, B.t0, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(NBX_EHIP);
+    int worst = NBX_OK;
+    for (int p = 0; p < nprob; ++p) {
+        const double *hs = h + p * NBX_SCAL_LEN;
+        nbx_pcg_result &r = results[p];
+        r = nbx_pcg_result{};
+        r.iters = (int)hs[NBX_S_ITER];
+        r.outer_iters = 1;
+        r.relres = hs[NBX_S_BB] > 0 ? std::sqrt(hs[NBX_S_RR] / hs[NBX_S_BB]) : 0.0;
+        const double fl = hs[NBX_S_FLAG];
+        r.flag = fl == 1.0 ? 1 : (fl == 2.0 ? 2 : 0);
+        r.seconds = wall;
+        double rb[2];
+        st = residual_f64(probs[p], b[p], x[p], nullptr, rb, s);
+        if (st != NBX_OK) return fail(st);
+        r.true_relres = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
+        if (solve_seconds)
+            solve_seconds[p] = rate_khz > 0 && stamps[p] > t0d
+                                   ? (stamps[p] - t0d) / (rate_khz * 1e3) : 0.0;
+        if (r.flag == 2) worst = NBX_EBREAKDOWN;
+        else if (r.flag != 1 && worst == NBX_OK) worst = NBX_NOT_CONVERGED;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
+        return fail(NBX_EHIP);
+    cleanup();
+    return worst;
+}

@@ -8,7 +8,7 @@
 // group sums in a fixed order and writes identical bits to all copies:
 // no atomics, deterministic, and bit-identical to a sequential sum in
 // ascending local order.
-#include "internal.hpp"
+#include "gs_kernels.hpp"
 
 #include <algorithm>
 #include <numeric>
@@ -25,11 +25,7 @@ __global__ void dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off,
     if (flag && *flag != 0.0) return;   // uniform: solve already finished
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
-    const int32_t b = off[g], e = off[g + 1];
-    T s = 0;
-    for (int32_t q = b; q < e; ++q) s += v[idx[q]];
-    if (apply_mask && gflag[g]) s = 0;
-    for (int32_t q = b; q < e; ++q) v[idx[q]] = s;
+    dssum_group<T>(g, off, idx, gflag, v, apply_mask);
 }
 
 template <typename T>

@@ -52,15 +52,16 @@ inline int red_blocks(int64_t n)
 
 // Start of a solve from x = 0 with right-hand side b (type TB, converted to
 // T): x = 0, r = b, z = dinv r, p = 0; partials of c r r and c r z.
+// Block blk of nblk (grid-stride within one vector).
 template <typename T, typename TB>
-__global__ void __launch_bounds__(kRedThreads)
-init_kernel(int64_t n, const TB *__restrict__ b, const T *__restrict__ dinv,
-            const uint8_t *__restrict__ info, T *__restrict__ x, T *__restrict__ r,
-            T *__restrict__ z, T *__restrict__ p, double *__restrict__ part)
+__device__ __forceinline__ void
+init_body(int64_t n, const TB *__restrict__ b, const T *__restrict__ dinv,
+          const uint8_t *__restrict__ info, T *__restrict__ x, T *__restrict__ r,
+          T *__restrict__ z, T *__restrict__ p, double *__restrict__ part, int64_t blk,
+          int64_t nblk)
 {
     double rr = 0, rz = 0;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t l = blk * blockDim.x + threadIdx.x; l < n; l += nblk * blockDim.x) {
         const T rv = (T)b[l], zv = dinv[l] * rv;
         const double c = cw(info[l]);
         x[l] = 0; r[l] = rv; z[l] = zv; p[l] = 0;
@@ -68,14 +69,34 @@ init_kernel(int64_t n, const TB *__restrict__ b, const T *__restrict__ dinv,
         rz += c * (double)rv * (double)zv;
     }
     block_sum2(rr, rz);
-    if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = rz; }
+    if (threadIdx.x == 0) { part[2 * blk] = rr; part[2 * blk + 1] = rz; }
+}
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kRedThreads)
+init_kernel(int64_t n, const TB *__restrict__ b, const T *__restrict__ dinv,
+            const uint8_t *__restrict__ info, T *__restrict__ x, T *__restrict__ r,
+            T *__restrict__ z, T *__restrict__ p, double *__restrict__ part)
+{
+    init_body<T, TB>(n, b, dinv, info, x, r, z, p, part, blockIdx.x, gridDim.x);
 }
 
 // scal <- fresh state: RR = BB = sum of the first partials, RHO = second,
 // STOP = rtol^2 BB (or -1), MAXIT, FLAG (converged at once if BB == 0).
+__device__ __forceinline__ void
+init_reduce_body(int nb, const double *__restrict__ part, double *__restrict__ scal,
+                 double rtol, int fixed, int max_iter);
+
 __global__ void __launch_bounds__(1024)
 init_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal,
                    double rtol, int fixed, int max_iter)
+{
+    init_reduce_body(nb, part, scal, rtol, fixed, max_iter);
+}
+
+__device__ __forceinline__ void
+init_reduce_body(int nb, const double *__restrict__ part, double *__restrict__ scal,
+                 double rtol, int fixed, int max_iter)
 {
     __shared__ double s[2][16];
     double a = 0, b = 0;
@@ -96,9 +117,10 @@ init_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__
     }
 }
 
-// R1: pap from the AX partials; alpha; breakdown check.
-__global__ void __launch_bounds__(1024)
-pap_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+// R1: pap from the AX partials; alpha; breakdown check.  One 1024-thread
+// block per scalar block.
+__device__ __forceinline__ void
+pap_reduce_body(int nb, const double *__restrict__ part, double *__restrict__ scal)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     __shared__ double s[16];
@@ -116,6 +138,12 @@ pap_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ 
     }
 }
 
+__global__ void __launch_bounds__(1024)
+pap_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+{
+    pap_reduce_body(nb, part, scal);
+}
+
 template <typename T> struct Vec;
 template <> struct Vec<double> {
     typedef double v __attribute__((ext_vector_type(2)));
@@ -131,11 +159,11 @@ template <> struct Vec<float> {
 // K3: x += alpha p; r -= alpha w; z = dinv r; partials of c r r and c r z.
 // Vector accesses of 16 bytes per lane, scalar tail.
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads)
-update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
-              const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
-              T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
-              const double *__restrict__ scal)
+__device__ __forceinline__ void
+update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
+            const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
+            T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
+            const double *__restrict__ scal, int64_t blk, int64_t nblk)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     using V = Vec<T>;
@@ -152,8 +180,7 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
     const typename V::iv *iv = reinterpret_cast<const typename V::iv *>(info);
     // every array is streamed once per iteration (and exceeds the caches at
     // benchmark sizes): non-temporal loads and stores throughout
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = blk * blockDim.x + threadIdx.x; q < nv; q += nblk * blockDim.x) {
         const typename V::v pq = __builtin_nontemporal_load(pv + q);
         const typename V::v wq = __builtin_nontemporal_load(wv + q);
         const typename V::v dq = __builtin_nontemporal_load(dv + q);
@@ -174,7 +201,7 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
         __builtin_nontemporal_store(rq, rv + q);
         __builtin_nontemporal_store(zq, zv + q);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         for (int64_t l = nv * W; l < n; ++l) {
             x[l] = fmaT(alpha, p[l], x[l]);
             const T rl = fmaT(-alpha, w[l], r[l]), zl = dinv[l] * rl;
@@ -185,12 +212,24 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
         }
     }
     block_sum2(rr, rz);
-    if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = rz; }
+    if (threadIdx.x == 0) { part[2 * blk] = rr; part[2 * blk + 1] = rz; }
 }
 
-// R3: rr, rho'; convergence / breakdown / iteration limit; beta.
-__global__ void __launch_bounds__(1024)
-rr_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
+              const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
+              T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
+              const double *__restrict__ scal)
+{
+    update_body<T>(n, p, w, dinv, info, x, r, z, part, scal, blockIdx.x, gridDim.x);
+}
+
+// R3: rr, rho'; convergence / breakdown / iteration limit; beta.  With
+// stamp, the device wall clock at convergence is stored there.
+__device__ __forceinline__ void
+rr_reduce_body(int nb, const double *__restrict__ part, double *__restrict__ scal,
+               double *__restrict__ stamp = nullptr)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     __shared__ double s[2][16];
@@ -214,7 +253,14 @@ rr_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ s
             scal[NBX_S_RHO] = rz;
             if (it >= scal[NBX_S_MAXIT]) scal[NBX_S_FLAG] = kFlagLimit;
         }
+        if (stamp && scal[NBX_S_FLAG] != 0.0) *stamp = (double)wall_clock64();
     }
+}
+
+__global__ void __launch_bounds__(1024)
+rr_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
+{
+    rr_reduce_body(nb, part, scal);
 }
 
 // Partials of c (b - w)^2 and c b^2 (FP64 residual of a refinement step);

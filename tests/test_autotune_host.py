@@ -1,0 +1,40 @@
+"""The tile table and the autotuner's cache on the host (no GPU needed:
+the table is host state of the library)."""
+import json
+
+import pytest
+
+import paper_2011_04981_amd as nbx
+from paper_2011_04981_amd import autotune
+
+
+def test_apply_and_load_cache(tmp_path):
+    old = {(p, N): nbx.get_tile(p, N) for p in (nbx.F64, nbx.F32) for N in (6, 8, 10, 12)}
+    try:
+        table = {"f64": {"6": {"epb": 1, "us": {}}, "10": {"epb": 4, "us": {}}},
+                 "f32": {"8": {"epb": 2, "us": {}}}}
+        path = autotune.save(table, str(tmp_path / "tiles.json"))
+        rec = json.load(open(path))
+        assert rec["arch"] == "gfx950"
+        loaded = autotune.load(path)
+        assert loaded == table
+        assert nbx.get_tile(nbx.F64, 6) == 1
+        assert nbx.get_tile(nbx.F64, 10) == 4
+        assert nbx.get_tile(nbx.F32, 8) == 2
+    finally:
+        for (p, N), e in old.items():
+            nbx.set_tile(p, N, e)
+
+
+def test_tile_table_rejects_invalid_entries():
+    with pytest.raises(nbx.NbxError):
+        nbx.set_tile(nbx.F64, 10, 3)
+    with pytest.raises(nbx.NbxError):
+        nbx.set_tile(nbx.F64, 17, 2)
+    with pytest.raises(nbx.NbxError):
+        nbx.set_tile(nbx.BF16, 10, 2)
+    assert nbx.get_tile(nbx.F64, 10) in (1, 2, 4)
+
+
+def test_missing_cache_is_ignored(tmp_path):
+    assert autotune.load(str(tmp_path / "absent.json")) is None

@@ -1,0 +1,97 @@
+"""Batched solves and the tile autotuner on the GPU.
+
+Batched results must be bit-identical to solving each problem alone (same
+kernel bodies, block counts and reduction order), and agree with the
+oracle like any standalone solve."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2011_04981_amd as nbx  # noqa: E402
+from paper_2011_04981_amd import autotune  # noqa: E402
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _problems():
+    """Uneven sizes and orders; random and sine right-hand sides."""
+    specs = [S.Brick(2, 2, 2, 6, ((0.03, 2, 2, 2),) * 3, "random", 11),
+             S.Brick(3, 2, 2, 8, ((0.05, 2, 2, 2),) * 3, "random", 12),
+             S.Brick(4, 4, 4, 10, ((0.05, 2, 2, 2),) * 3, "sine", 0),
+             S.Brick(2, 2, 1, 12, ((0.02, 2, 2, 2),) * 3, "random", 13),
+             S.Brick(5, 3, 2, 6, S.NO_DEFORM, "sine", 0),
+             S.Brick(3, 3, 3, 8, ((0.08, 2, 2, 2),) * 3, "random", 14)]
+    out = []
+    for b in specs:
+        f = None
+        if b.rhs == "random":
+            f = torch.as_tensor(S.rhs_values(b)).cuda()
+        out.append((b, nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array(), f=f)))
+    return out
+
+
+def test_batched_bit_identical_to_standalone():
+    probs = _problems()
+    refs = []
+    for b, st in probs:
+        x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=3000, check_every=10)
+        assert r.status == 0
+        refs.append((host(x), r.iters))
+    xs, res, lat = nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                                   rtol=1e-10, max_iter=3000, check_every=10)
+    for (b, st), (xr, it), x, r in zip(probs, refs, xs, res):
+        print(f"{b.name or b}: standalone {it} it, batched {r.iters} it")
+        assert r.status == 0 and r.flag == 1
+        assert r.iters == it
+        assert np.array_equal(host(x), xr)
+        assert r.true_relres <= 1e-9
+    # latencies: positive, within the batch wall time, slowest problem last
+    wall = res[0].seconds
+    assert all(0 < t <= wall * 1.05 for t in lat)
+    # every graph iteration advances each unconverged problem by one
+    # iteration, so the problem needing the most iterations finishes last
+    iters = [r.iters for r in res]
+    assert lat[int(np.argmax(iters))] >= 0.99 * max(lat)
+
+
+def test_batched_matches_oracle():
+    b = S.Brick(3, 2, 2, 8, ((0.05, 2, 2, 2),) * 3, "random", 21)
+    f = S.rhs_values(b)
+    P = O.setup(b, rhs_values=f)
+    ref = O.pcg(P, max_iter=3000, rtol=1e-10)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array(), f=torch.as_tensor(f).cuda())
+    st2 = nbx.setup_brick(3, 3, 3, 6)
+    xs, res, lat = nbx.pcg_batched([st.problem, st2.problem], [st.b, st2.b], rtol=1e-10,
+                                   max_iter=3000)
+    assert abs(res[0].iters - ref.iters) <= 1
+    x = host(xs[0]).reshape(-1)
+    assert np.abs(x - ref.x).max() <= 1e-8 * np.abs(ref.x).max()
+
+
+def test_batched_fixed_iterations_and_limits():
+    probs = _problems()[:3]
+    xs, res, lat = nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                                   max_iter=25, fixed_iters=1, check_every=10)
+    assert all(r.iters == 25 and r.flag == 0 for r in res)
+
+
+def test_autotuner_picks_a_valid_tile_and_is_result_neutral():
+    old = nbx.get_tile(nbx.F64, 8)
+    try:
+        table = autotune.tune(Ns=(8,), precs=(nbx.F64,), nodes=400_000, reps=3)
+        row = table["f64"]["8"]
+        assert row["epb"] in (1, 2, 4) and nbx.get_tile(nbx.F64, 8) == row["epb"]
+        assert set(row["us"]) <= {"1", "2", "4"} and all(v > 0 for v in row["us"].values())
+    finally:
+        nbx.set_tile(nbx.F64, 8, old)
