@@ -251,6 +251,51 @@ int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b, double *c
                     int nprob, const nbx_pcg_opts *opts, nbx_pcg_result *results,
                     double *solve_seconds, void *stream);
 
+/* ------------------------------------------- element-local network (BF16) --
+ * Matrix-core kernels for the learned preconditioner's network (reduced
+ * precision is the paper's further work, Section V; the network itself is
+ * not in the paper).  BF16 values are passed as raw 16-bit words
+ * (uint16_t arrays); accumulation is FP32. */
+
+/* C[M x N] (FP32, row-major, ldc) = op(A)[M x K] op(B)[K x N] with BF16
+ * operands: A(m,k) = trans_a ? A[k*lda + m] : A[m*lda + k], B(k,n) =
+ * trans_b ? B[n*ldb + k] : B[k*ldb + n].  M, N multiples of 64, K a
+ * multiple of 32, lda and ldb multiples of 8, otherwise NBX_EINVAL.
+ * Async. */
+int nbx_gemm_bf16(int trans_a, int trans_b, int M, int N, int K, const void *A, int lda,
+                  const void *B, int ldb, float *C, int ldc, void *stream);
+
+typedef struct nbx_mlp nbx_mlp;
+
+/* A 3-layer perceptron n_in -> n_hidden -> n_hidden -> n_out with ReLU,
+ * for batches of up to max_batch rows (multiple of 64; n_hidden a multiple
+ * of 64).  Inputs and outputs are padded to in_pad / out_pad (multiples of
+ * 64).  Parameters live in one FP32 arena of n_params floats:
+ * W1[n_hidden][in_pad], b1[n_hidden], W2[n_hidden][n_hidden], b2[n_hidden],
+ * W3[out_pad][n_hidden], b3[out_pad] (row-major, W[out][in]); a BF16 copy
+ * feeds the products.  Allocates; synchronous.  All parameters start at 0. */
+int nbx_mlp_create(int n_in, int n_hidden, int n_out, int max_batch, nbx_mlp **out);
+int nbx_mlp_destroy(nbx_mlp *mlp);
+int nbx_mlp_shape(nbx_mlp *mlp, int *in_pad, int *out_pad, int64_t *n_params);
+/* Copies a parameter arena (device FP32) in, refreshes the BF16 copy and
+ * resets the optimiser state.  Async. */
+int nbx_mlp_set_params(nbx_mlp *mlp, const float *params, void *stream);
+/* Copies the parameters and/or the last gradients out (device, may be
+ * NULL).  Async. */
+int nbx_mlp_get_params(nbx_mlp *mlp, float *params, float *grads, void *stream);
+/* Y[B][out_pad] (FP32) = network(X[B][in_pad] BF16); B a multiple of 64,
+ * at most max_batch.  Async. */
+int nbx_mlp_forward(nbx_mlp *mlp, const void *X, int B, float *Y, void *stream);
+/* Gradients of the mean squared error sum_{b, j < n_out} (Y - T)^2 / (B n_out)
+ * for targets T[B][out_pad] (FP32) into the gradient arena; *loss (device,
+ * may be NULL) receives the loss.  Async. */
+int nbx_mlp_grad(nbx_mlp *mlp, const void *X, const float *T, int B, double *loss,
+                 void *stream);
+/* nbx_mlp_grad, then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with
+ * learning rate lr on the FP32 master parameters.  Async. */
+int nbx_mlp_train_step(nbx_mlp *mlp, const void *X, const float *T, int B, float lr,
+                       double *loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

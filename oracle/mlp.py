@@ -1,0 +1,186 @@
+"""FP64 reference for the element-local network of the learned
+preconditioner and for flexible PCG.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  The network is not in
+the paper; this follows the textbook definitions: a 3-layer perceptron
+y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, the chain rule for its gradients
+(hand-written, pinned by central finite differences), Adam (Kingma & Ba
+2015, pinned by its first-step property), and flexible PCG (Notay 2000:
+beta = <r_new, z_new - z_old> / <r_old, z_old>, which equals PCG for a fixed
+SPD preconditioner).
+
+Parameters use one flat arena: W1[hid][in_pad], b1[hid], W2[hid][hid],
+b2[hid], W3[out_pad][hid], b3[out_pad] (row-major W[out][in]).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def pad64(n: int) -> int:
+    return (n + 63) // 64 * 64
+
+
+class Shape:
+    def __init__(self, n_in: int, n_hid: int, n_out: int):
+        self.n_in, self.n_hid, self.n_out = n_in, n_hid, n_out
+        self.in_pad, self.out_pad = pad64(n_in), pad64(n_out)
+        h, i, o = n_hid, self.in_pad, self.out_pad
+        self.sizes = [h * i, h, h * h, h, o * h, o]
+        self.n_params = sum(self.sizes)
+
+    def unpack(self, p):
+        h, i, o = self.n_hid, self.in_pad, self.out_pad
+        out, k = [], 0
+        for sz, shp in zip(self.sizes, [(h, i), (h,), (h, h), (h,), (o, h), (o,)]):
+            out.append(np.asarray(p[k:k + sz], dtype=np.float64).reshape(shp))
+            k += sz
+        return out
+
+    def pack(self, parts):
+        return np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in parts])
+
+    def from_init(self, init: dict):
+        """Arena from synthetic.mlp_init weights (unpadded), zero-padded."""
+        h, i, o = self.n_hid, self.in_pad, self.out_pad
+        W1 = np.zeros((h, i)); W1[:, :self.n_in] = init["W1"]
+        W3 = np.zeros((o, h)); W3[:self.n_out] = init["W3"]
+        b3 = np.zeros(o); b3[:self.n_out] = init["b3"]
+        return self.pack([W1, init["b1"], init["W2"], init["b2"], W3, b3])
+
+
+def relu(a):
+    return np.maximum(a, 0.0)
+
+
+def forward(shape: Shape, params, X):
+    """(H1, H2, Y) for X[B][in_pad]."""
+    W1, b1, W2, b2, W3, b3 = shape.unpack(params)
+    X = np.asarray(X, dtype=np.float64)
+    H1 = relu(X @ W1.T + b1)
+    H2 = relu(H1 @ W2.T + b2)
+    Y = H2 @ W3.T + b3
+    return H1, H2, Y
+
+
+def loss_and_grad(shape: Shape, params, X, T):
+    """Mean squared error over the first n_out outputs and its gradient
+    with respect to every parameter (chain rule, relu'(0) = 0)."""
+    W1, b1, W2, b2, W3, b3 = shape.unpack(params)
+    X = np.asarray(X, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    B = X.shape[0]
+    H1, H2, Y = forward(shape, params, X)
+    D = np.zeros_like(Y)
+    D[:, :shape.n_out] = Y[:, :shape.n_out] - T[:, :shape.n_out]
+    loss = float(np.sum(D ** 2) / (B * shape.n_out))
+    dY = 2.0 * D / (B * shape.n_out)
+    dW3 = dY.T @ H2
+    db3 = dY.sum(axis=0)
+    dH2 = (dY @ W3) * (H2 > 0)
+    dW2 = dH2.T @ H1
+    db2 = dH2.sum(axis=0)
+    dH1 = (dH2 @ W2) * (H1 > 0)
+    dW1 = dH1.T @ X
+    db1 = dH1.sum(axis=0)
+    return loss, shape.pack([dW1, db1, dW2, db2, dW3, db3])
+
+
+def adam_step(params, grads, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update; returns (params, m, v)."""
+    m = b1 * m + (1 - b1) * grads
+    v = b2 * v + (1 - b2) * grads ** 2
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_bits(a):
+    """bfloat16 bit patterns (uint16) of a, ties to even."""
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+# ------------------------------------------------------------ flexible PCG
+
+def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
+    """Flexible preconditioned CG with c-weighted dots:
+    r = b - A x, z = M(r), p = z; per iteration
+    w = A p, alpha = <r,z>/<p,w>, x += alpha p, r -= alpha w, z' = M(r),
+    beta = <r, z' - z> / <r_old, z>, p = z' + beta p.
+    Returns (x, iterations, relative residual history)."""
+    def dot(a, b_):
+        return float(np.sum(c * a * b_))
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    z = precond(r)
+    p = z.copy()
+    rho = dot(r, z)
+    bb = dot(b, b)
+    hist = []
+    for k in range(max_iter):
+        w = apply_A(p)
+        alpha = rho / dot(p, w)
+        x += alpha * p
+        r -= alpha * w
+        rel = np.sqrt(dot(r, r) / bb)
+        hist.append(rel)
+        if rel <= rtol:
+            return x, k + 1, np.array(hist)
+        zn = precond(r)
+        rho_new = dot(r, zn)
+        beta = (rho_new - dot(r, z)) / rho
+        rho = rho_new
+        z = zn
+        p = z + beta * p
+    return x, max_iter, np.array(hist)
+
+
+# -------------------------------------------- learned preconditioner (FP64)
+
+def element_features(Gmat, N: int):
+    """Per element: the six element-mean factors divided by gd, the mean of
+    the three diagonal factors over the element, and gd itself."""
+    G = np.asarray(Gmat).reshape(-1, 6, N ** 3)
+    means = G.mean(axis=2)                       # [E][6]
+    gd = (means[:, 0] + means[:, 3] + means[:, 5]) / 3.0
+    return means / gd[:, None], gd
+
+
+def features(r, gfeat, gd, N: int, in_pad: int):
+    """Network input per element: r_e / ||r_e|| (N^3 values), the six
+    normalised factors, zeros to in_pad; and the output scale
+    s_e = ||r_e|| / gd_e."""
+    R = np.asarray(r).reshape(-1, N ** 3)
+    nrm = np.sqrt(np.sum(R ** 2, axis=1))
+    safe = np.where(nrm > 0, nrm, 1.0)
+    X = np.zeros((R.shape[0], in_pad))
+    X[:, :N ** 3] = np.where(nrm[:, None] > 0, R / safe[:, None], 0.0)
+    X[:, N ** 3:N ** 3 + 6] = gfeat
+    return X, nrm / gd
+
+
+def apply_learned(P, shape: Shape, params, r, gfeat, gd, round_inputs=False):
+    """z = dinv r + mask(dssum(c * s_e * f(x_e))) in FP64.  With
+    round_inputs the network inputs and weights are rounded to bfloat16
+    first (the GPU's operands)."""
+    from . import mask
+    N = P.N
+    X, s = features(r, gfeat, gd, N, shape.in_pad)
+    prm = params
+    if round_inputs:
+        X = bf16_round(X)
+        W1, b1, W2, b2, W3, b3 = shape.unpack(params)
+        prm = shape.pack([bf16_round(W1), b1, bf16_round(W2), b2, bf16_round(W3), b3])
+    _, _, Y = forward(shape, prm, X)
+    zl = (P.c.reshape(-1, N ** 3) * s[:, None] * Y[:, :N ** 3]).reshape(-1)
+    return P.dinv * r + mask(P.bnd, P.gs.dssum(zl))

@@ -88,6 +88,15 @@ def lib():
         "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
         "nbx_pcg_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32,
                              C.POINTER(PcgOpts), C.POINTER(PcgResult), C.POINTER(dp), vp], i32),
+        "nbx_gemm_bf16": ([i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, vp], i32),
+        "nbx_mlp_create": ([i32, i32, i32, i32, C.POINTER(vp)], i32),
+        "nbx_mlp_destroy": ([vp], i32),
+        "nbx_mlp_shape": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)], i32),
+        "nbx_mlp_set_params": ([vp, vp, vp], i32),
+        "nbx_mlp_get_params": ([vp, vp, vp, vp], i32),
+        "nbx_mlp_forward": ([vp, vp, i32, vp, vp], i32),
+        "nbx_mlp_grad": ([vp, vp, vp, i32, vp, vp], i32),
+        "nbx_mlp_train_step": ([vp, vp, vp, i32, C.c_float, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -455,3 +464,88 @@ def pcg_batched(problems, bs, xs=None, stream=None, **opts):
     out = [SolveResult(st, r.iters, r.outer_iters, r.relres, r.true_relres, r.fell_back,
                        r.flag, r.seconds) for r in res]
     return xs, out, list(lat)
+
+
+# ------------------------------------------------------- BF16 network
+
+def gemm_bf16(A, B, trans_a=False, trans_b=False, stream=None):
+    """C = op(A) op(B) in FP32 from bfloat16 operands (matrix cores)."""
+    torch = _torch()
+    if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
+        raise TypeError("operands must be bfloat16")
+    M, K = (A.shape[1], A.shape[0]) if trans_a else (A.shape[0], A.shape[1])
+    Kb, N = (B.shape[1], B.shape[0]) if trans_b else (B.shape[0], B.shape[1])
+    if K != Kb:
+        raise ValueError("inner dimensions differ")
+    Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib().nbx_gemm_bf16(int(trans_a), int(trans_b), M, N, K, _dptr(A), A.shape[1],
+                               _dptr(B), B.shape[1], _dptr(Cm), N, _stream(stream)),
+           "nbx_gemm_bf16")
+    return Cm
+
+
+class Mlp:
+    """Handle of the element-local network (see include/nbx.h)."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, max_batch: int):
+        h = C.c_void_p()
+        _check(lib().nbx_mlp_create(n_in, n_hidden, n_out, max_batch, C.byref(h)),
+               "nbx_mlp_create")
+        self._h = h
+        ip, op, npar = C.c_int(), C.c_int(), C.c_int64()
+        _check(lib().nbx_mlp_shape(h, C.byref(ip), C.byref(op), C.byref(npar)), "nbx_mlp_shape")
+        self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+        self.in_pad, self.out_pad, self.n_params = ip.value, op.value, npar.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbx_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        torch = _torch()
+        _check(lib().nbx_mlp_set_params(self._h, _dptr(params, torch.float32), _stream(stream)),
+               "nbx_mlp_set_params")
+
+    def get_params(self, grads=False, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        if grads:
+            _check(lib().nbx_mlp_get_params(self._h, None, _dptr(out), _stream(stream)),
+                   "nbx_mlp_get_params")
+        else:
+            _check(lib().nbx_mlp_get_params(self._h, _dptr(out), None, _stream(stream)),
+                   "nbx_mlp_get_params")
+        return out
+
+    def forward(self, X, stream=None):
+        torch = _torch()
+        Y = torch.empty((X.shape[0], self.out_pad), dtype=torch.float32, device=X.device)
+        _check(lib().nbx_mlp_forward(self._h, _dptr(X, torch.bfloat16), X.shape[0], _dptr(Y),
+                                     _stream(stream)), "nbx_mlp_forward")
+        return Y
+
+    def grad(self, X, T, stream=None):
+        torch = _torch()
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+        _check(lib().nbx_mlp_grad(self._h, _dptr(X, torch.bfloat16), _dptr(T, torch.float32),
+                                  X.shape[0], _dptr(loss), _stream(stream)), "nbx_mlp_grad")
+        return loss
+
+    def train_step(self, X, T, lr: float, stream=None):
+        torch = _torch()
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+        _check(lib().nbx_mlp_train_step(self._h, _dptr(X, torch.bfloat16),
+                                        _dptr(T, torch.float32), X.shape[0], float(lr),
+                                        _dptr(loss), _stream(stream)), "nbx_mlp_train_step")
+        return loss
