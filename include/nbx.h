@@ -296,6 +296,40 @@ int nbx_mlp_grad(nbx_mlp *mlp, const void *X, const float *T, int B, double *los
 int nbx_mlp_train_step(nbx_mlp *mlp, const void *X, const float *T, int B, float lr,
                        double *loss, void *stream);
 
+/* ------------------------------------------ learned preconditioner (flexible CG) --
+ * M(r) = dinv r + mask(dssum(c * s_e * f(x_e))): per element e the network
+ * f (n_in = N^3 + 6, n_out = N^3) sees x_e = [r_e / ||r_e||, the six
+ * element-mean geometric factors divided by gd_e] and its output is scaled
+ * by s_e = ||r_e|| / gd_e (gd_e = element mean of g1, g4, g6); c =
+ * 1/multiplicity.  Zero network output gives back the Jacobi
+ * preconditioner (the paper's "simple preconditioner", Section II-B). */
+typedef struct nbx_lp nbx_lp;
+
+/* Binds a problem and a network (both must outlive the handle), computes
+ * the per-element geometric features, allocates feature/output buffers.
+ * NBX_EINVAL if the network's sizes do not match N.  Synchronous. */
+int nbx_lp_create(nbx_problem *p, nbx_mlp *mlp, nbx_lp **out, void *stream);
+int nbx_lp_destroy(nbx_lp *lp);
+/* gfeat[E][8]: six normalised factors, gd, 0.  Async. */
+int nbx_lp_geom_features(nbx_lp *lp, float *gfeat, void *stream);
+/* z = M(r) (device FP64 vectors, r != z).  Async. */
+int nbx_lp_apply(nbx_lp *lp, const double *r, double *z, void *stream);
+/* Training rows from an FP64 CG state: for the nsel elements in elems
+ * (device int32), X[row][in_pad] (BF16 features as above) and
+ * T[row][out_pad] = ((xstar - x) - dinv r) / s_e on the element's nodes,
+ * 0 elsewhere.  An index outside [0, E) yields an all-zero row.  Async. */
+int nbx_lp_samples(nbx_lp *lp, const double *r, const double *xstar, const double *x,
+                   const int32_t *elems, int nsel, void *X, float *T, void *stream);
+/* Copies the recurrence residual of the problem's last solve. Async. */
+int nbx_problem_residual(nbx_problem *p, double *r, void *stream);
+/* Flexible PCG (Notay: beta = <r', z' - z> / <r, z>) with M from x = 0.  If
+ * it breaks down or reaches opts->max_iter (pass the Jacobi-PCG iteration
+ * count to enforce "no worse than Jacobi") without meeting rtol, Jacobi-PCG
+ * finishes the solve from the current x and res->fell_back = 1.
+ * Synchronous; returns like nbx_pcg. */
+int nbx_pcg_learned(nbx_lp *lp, const double *b, double *x, const nbx_pcg_opts *opts,
+                    nbx_pcg_result *res, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,12 +112,22 @@ def bf16_bits(a):
 
 # ------------------------------------------------------------ flexible PCG
 
+class FpcgBreakdown(ArithmeticError):
+    """<r, M(r)> or <p, A p> was not positive: the CG step is undefined
+    (a preconditioner that is not positive on r)."""
+
+    def __init__(self, iteration: int):
+        super().__init__(f"flexible PCG breakdown at iteration {iteration}")
+        self.iteration = iteration
+
+
 def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
     """Flexible preconditioned CG with c-weighted dots:
     r = b - A x, z = M(r), p = z; per iteration
     w = A p, alpha = <r,z>/<p,w>, x += alpha p, r -= alpha w, z' = M(r),
     beta = <r, z' - z> / <r_old, z>, p = z' + beta p.
-    Returns (x, iterations, relative residual history)."""
+    Returns (x, iterations, relative residual history); raises
+    FpcgBreakdown when <r, z> or <p, w> is not positive."""
     def dot(a, b_):
         return float(np.sum(c * a * b_))
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -127,9 +137,14 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
     rho = dot(r, z)
     bb = dot(b, b)
     hist = []
+    if not rho > 0:
+        raise FpcgBreakdown(0)
     for k in range(max_iter):
         w = apply_A(p)
-        alpha = rho / dot(p, w)
+        pw = dot(p, w)
+        if not pw > 0:
+            raise FpcgBreakdown(k)
+        alpha = rho / pw
         x += alpha * p
         r -= alpha * w
         rel = np.sqrt(dot(r, r) / bb)
@@ -138,6 +153,8 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
             return x, k + 1, np.array(hist)
         zn = precond(r)
         rho_new = dot(r, zn)
+        if not rho_new > 0:
+            raise FpcgBreakdown(k + 1)
         beta = (rho_new - dot(r, z)) / rho
         rho = rho_new
         z = zn

@@ -549,3 +549,85 @@ class Mlp:
                                         _dptr(T, torch.float32), X.shape[0], float(lr),
                                         _dptr(loss), _stream(stream)), "nbx_mlp_train_step")
         return loss
+
+
+class LearnedPrecond:
+    """Learned element-local preconditioner bound to a problem and a network
+    (nbx_lp_*): apply, training samples, flexible PCG with Jacobi fallback."""
+
+    def __init__(self, problem: "Problem", net: Mlp, stream=None):
+        L = lib()
+        for name, args in {"nbx_lp_create": [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
+                                             C.c_void_p],
+                           "nbx_lp_destroy": [C.c_void_p],
+                           "nbx_lp_geom_features": [C.c_void_p, C.c_void_p, C.c_void_p],
+                           "nbx_lp_apply": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                           "nbx_lp_samples": [C.c_void_p] * 5 + [C.c_int] + [C.c_void_p] * 3,
+                           "nbx_problem_residual": [C.c_void_p] * 3,
+                           "nbx_pcg_learned": [C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.POINTER(PcgOpts), C.POINTER(PcgResult),
+                                               C.c_void_p]}.items():
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = C.c_int
+        h = C.c_void_p()
+        _check(L.nbx_lp_create(problem._h, net.handle, C.byref(h), _stream(stream)),
+               "nbx_lp_create")
+        self._h, self.problem, self.net = h, problem, net
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbx_lp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def geom_features(self, stream=None):
+        torch = _torch()
+        g = torch.empty((self.problem.E, 8), dtype=torch.float32, device="cuda")
+        _check(lib().nbx_lp_geom_features(self._h, _dptr(g), _stream(stream)),
+               "nbx_lp_geom_features")
+        return g
+
+    def apply(self, r, stream=None):
+        torch = _torch()
+        z = torch.empty_like(r)
+        _check(lib().nbx_lp_apply(self._h, _dptr(r, torch.float64), _dptr(z), _stream(stream)),
+               "nbx_lp_apply")
+        return z
+
+    def samples(self, r, xstar, x, elems, stream=None):
+        """(X [n, in_pad] bf16, T [n, out_pad] f32) for the element indices."""
+        torch = _torch()
+        n = elems.numel()
+        X = torch.empty((n, self.net.in_pad), dtype=torch.bfloat16, device="cuda")
+        T = torch.empty((n, self.net.out_pad), dtype=torch.float32, device="cuda")
+        _check(lib().nbx_lp_samples(self._h, _dptr(r, torch.float64),
+                                    _dptr(xstar, torch.float64), _dptr(x, torch.float64),
+                                    _dptr(elems, torch.int32), n, _dptr(X), _dptr(T),
+                                    _stream(stream)), "nbx_lp_samples")
+        return X, T
+
+    def residual(self, stream=None):
+        """The recurrence residual left by the problem's last solve."""
+        torch = _torch()
+        r = torch.empty((self.problem.E, self.problem.N ** 3), dtype=torch.float64,
+                        device="cuda")
+        _check(lib().nbx_problem_residual(self.problem._h, _dptr(r), _stream(stream)),
+               "nbx_problem_residual")
+        return r
+
+    def pcg(self, b, x=None, stream=None, **opts):
+        torch = _torch()
+        x = torch.empty_like(b) if x is None else x
+        o = default_opts(**opts)
+        r = PcgResult()
+        st = lib().nbx_pcg_learned(self._h, _dptr(b, torch.float64), _dptr(x, torch.float64),
+                                   C.byref(o), C.byref(r), _stream(stream))
+        if st < 0 and st != -5:
+            raise NbxError(st, "nbx_pcg_learned")
+        return x, SolveResult(st, r.iters, r.outer_iters, r.relres, r.true_relres,
+                              r.fell_back, r.flag, r.seconds)

@@ -246,6 +246,8 @@ int gemm_bf16(int ta, int tb, int epi, int M, int N, int K, const uint16_t *A, i
     return gemm(ta, tb, epi, M, N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, s);
 }
 
+int mlp_forward_rows(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s);
+
 }  // namespace nbx
 
 // ----------------------------------------------------------------- handle
@@ -340,6 +342,21 @@ int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream
 }
 
 }  // namespace
+
+int mlp_forward_rows(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s)
+{
+    if (B < 64 || B % 64 || B > P->max_batch) return NBX_EINVAL;
+    return mlp_forward(P, X, B, Y, s);
+}
+
+int mlp_dims(nbx_mlp *P, int *n_in, int *n_out, int *in_pad, int *out_pad, int *max_batch)
+{
+    if (!P) return NBX_EINVAL;
+    *n_in = P->n_in; *n_out = P->n_out; *in_pad = P->in_pad; *out_pad = P->out_pad;
+    *max_batch = P->max_batch;
+    return NBX_OK;
+}
+
 }  // namespace nbx
 
 using namespace nbx;

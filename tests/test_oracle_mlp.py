@@ -75,6 +75,23 @@ def test_fpcg_with_jacobi_equals_pcg():
     assert np.abs(x - ref.x).max() <= 1e-9 * np.abs(ref.x).max()
 
 
+def test_fpcg_detects_breakdown():
+    # M = -Jacobi is negative definite: <r, M r> < 0 at once
+    P = O.setup(S.scaled_c2_brick(2, 4))
+    with pytest.raises(M.FpcgBreakdown) as ei:
+        M.fpcg(P.apply_A, lambda r: -P.dinv * r, P.b, P.c, max_iter=50)
+    assert ei.value.iteration == 0
+    # a preconditioner that turns indefinite after the first step
+    calls = []
+
+    def flip(r):
+        calls.append(1)
+        return P.dinv * r if len(calls) == 1 else -P.dinv * r
+    with pytest.raises(M.FpcgBreakdown) as ei:
+        M.fpcg(P.apply_A, flip, P.b, P.c, max_iter=50)
+    assert ei.value.iteration == 1
+
+
 def test_learned_preconditioner_with_zero_network_is_jacobi():
     b = S.Brick(2, 2, 2, 6, ((0.05, 2, 2, 2),) * 3)
     P = O.setup(b)
