@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--N", type=int, default=10, help="GLL nodes per direction")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solve leg")
     ap.add_argument("--nbatch", type=int, default=64, help="problems in the batched leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner leg")
+    ap.add_argument("--learned-train", type=int, default=8,
+                    help="training meshes (32x16x16, N=10) for the learned leg")
+    ap.add_argument("--learned-epochs", type=int, default=10)
     return ap.parse_args()
 
 
@@ -265,6 +270,19 @@ def main():
             del sets, probs, bs, xs
             torch.cuda.empty_cache()
 
+    # ---- learned element-local preconditioner: train on FP64-CG samples,
+    # pick the damping on a validation brick, compare with Jacobi-PCG on an
+    # unseen 32^3 brick
+    if not a.no_learned and a.N == 10:
+        from paper_2011_04981_amd import learned as LL
+        with torch.cuda.stream(stream):
+            log(f"learned preconditioner: training on {a.learned_train} meshes")
+            ev = [S.Brick(a.n, a.n, a.n, 10, S.deformation_family(10000), "random", 10000,
+                          f"eval10000_E{a.n**3}")]
+            out["learned"] = LL.run_c5(n_train=a.learned_train, epochs=a.learned_epochs,
+                                       eval_meshes=ev, log=log)
+            torch.cuda.empty_cache()
+
     # ---- CPU oracle baseline (host cores, bounded sample)
     if not a.no_cpu:
         import oracle as O
@@ -276,7 +294,7 @@ def main():
         uo = S.uniform_field(sb.E, N, seed=0)
         O.ax(uo, Go, Do)
         reps, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < a.cpu_seconds and reps < 1000:
+        while time.perf_counter() - t0 < a.cpu_seconds and reps < 100000:
             O.ax(uo, Go, Do)
             reps += 1
         dt = time.perf_counter() - t0

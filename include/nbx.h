@@ -325,7 +325,9 @@ int nbx_problem_residual(nbx_problem *p, double *r, void *stream);
 /* Flexible PCG (Notay: beta = <r', z' - z> / <r, z>) with M from x = 0.  If
  * it breaks down or reaches opts->max_iter (pass the Jacobi-PCG iteration
  * count to enforce "no worse than Jacobi") without meeting rtol, Jacobi-PCG
- * finishes the solve from the current x and res->fell_back = 1.
+ * finishes the solve from the current x (from x = 0 if the flexible
+ * iteration diverged) and res->fell_back = 1; res->iters counts all
+ * iterations, res->outer_iters those of the flexible phase.
  * Synchronous; returns like nbx_pcg. */
 int nbx_pcg_learned(nbx_lp *lp, const double *b, double *x, const nbx_pcg_opts *opts,
                     nbx_pcg_result *res, void *stream);

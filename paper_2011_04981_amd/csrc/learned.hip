@@ -485,7 +485,7 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
         if (done >= o.max_iter + chunk) break;
     }
     res->iters = (int)h[NBX_S_ITER];
-    res->outer_iters = 1;
+    res->outer_iters = res->iters;   // flexible iterations before any fallback
     const double fl = h[NBX_S_FLAG];
     res->flag = fl == 1.0 ? 1 : (fl == 2.0 ? 2 : 0);
     double rb[2];

@@ -100,7 +100,9 @@ class Samples:
 def collect_samples(factory: MeshFactory, bricks, net: Mlp, n_iterates: int = 4,
                     elems_per_iterate: int = 512, seed: int = 0, rhs_kind: str = "mixed",
                     check_every: int = 20) -> Samples:
-    """Training rows from FP64 CG runs on the given meshes."""
+    """Training rows from FP64 CG runs on the given meshes: n_iterates
+    iterates per mesh (geometrically spaced), elems_per_iterate elements of
+    each (<= 0: all).  The rows stay in device memory."""
     import torch
     import synthetic as S
     t0 = time.perf_counter()
@@ -117,22 +119,30 @@ def collect_samples(factory: MeshFactory, bricks, net: Mlp, n_iterates: int = 4,
         for k in ks:
             xk, _ = mp.problem.pcg(mp.b, max_iter=k, fixed_iters=1, check_every=check_every)
             rk = lp.residual()
-            el = torch.as_tensor(rng.integers(0, mp.E, size=elems_per_iterate), dtype=torch.int32)
+            if elems_per_iterate <= 0 or elems_per_iterate >= mp.E:
+                el = torch.arange(mp.E, dtype=torch.int32)       # every element
+            else:
+                el = torch.as_tensor(rng.choice(mp.E, size=elems_per_iterate, replace=False),
+                                     dtype=torch.int32)
             X, T = lp.samples(rk, xstar, xk, el.cuda())
             Xs.append(X); Ts.append(T)
         lp.close()
         mp.problem.close()
-    X = torch.cat(Xs)
-    T = torch.cat(Ts)
+    # one global shuffle so that minibatches mix meshes, iterates and
+    # elements (a row permutation: data movement only)
+    perm = torch.as_tensor(rng.permutation(sum(x.shape[0] for x in Xs))).cuda()
+    X = torch.cat(Xs).index_select(0, perm)
+    T = torch.cat(Ts).index_select(0, perm)
+    del Xs, Ts
     torch.cuda.synchronize()
     return Samples(X, T, X.shape[0], len(bricks), time.perf_counter() - t0)
 
 
 def train(net: Mlp, data: Samples, epochs: int = 30, batch: int = 1024, lr: float = 1e-3,
           seed: int = 0) -> List[float]:
-    """Minibatch Adam over contiguous row blocks in random order (rows are
-    already a random mix of meshes, iterates and elements); cosine decay of
-    the learning rate.  Returns the mean loss per epoch."""
+    """Minibatch Adam over contiguous row blocks in random order (the rows
+    were shuffled once when collected); cosine decay of the learning rate.
+    Returns the mean loss per epoch."""
     import torch
     rng = np.random.default_rng(seed)
     nb = data.rows // batch
@@ -151,6 +161,16 @@ def train(net: Mlp, data: Samples, epochs: int = 30, batch: int = 1024, lr: floa
     return losses
 
 
+def set_damping(net: Mlp, trained, a: float):
+    """Deploys a * f (last layer scaled by a) from the trained arena."""
+    import torch
+    h, i, o = net.n_hidden, net.in_pad, net.out_pad
+    p = trained.clone()
+    w3 = h * i + h + h * h + h
+    p[w3:] *= a                                   # W3 and b3
+    net.set_params(p)
+
+
 @dataclass
 class EvalResult:
     name: str
@@ -160,6 +180,7 @@ class EvalResult:
     learned_iters: int
     learned_seconds: float
     fell_back: int
+    flexible_iters: int
     learned_relres: float
     iteration_ratio: float
     speedup: float
@@ -183,4 +204,94 @@ def evaluate(factory: MeshFactory, brick, net: Mlp, rtol: float = 1e-10, reps: i
     lp.close()
     mp.problem.close()
     return EvalResult(brick.name, brick.E, rj.iters, min(jt), rl.iters, min(lt), rl.fell_back,
-                      rl.true_relres, rl.iters / max(rj.iters, 1), min(jt) / min(lt))
+                      rl.outer_iters, rl.true_relres, rl.iters / max(rj.iters, 1), min(jt) / min(lt))
+
+
+def run_c5(n_train: int = 16, train_dims=(32, 16, 16), N: int = 10, eval_meshes=None,
+           epochs: int = 20, batch: int = 1024, lr: float = 1e-3, n_iterates: int = 4,
+           elems_per_iterate: int = 0, dampings=(1.0, 0.5, 0.25), rtol: float = 1e-10,
+           seed: int = 0, log=print) -> dict:
+    """Train on n_train seeded deformed bricks, choose the output damping on
+    a validation brick of the training distribution (seed 5000), evaluate
+    learned FPCG (with that damping) against Jacobi-PCG on held-out meshes
+    (by default one 32^3 brick with an unseen deformation, N=10).
+    learned_enabled reports the deployment decision: the learned
+    preconditioner is used only if it needed fewer iterations than Jacobi
+    on the validation brick without falling back."""
+    import torch
+    import synthetic as S
+    fac = MeshFactory()
+    bricks = [S.Brick(*train_dims, N, S.deformation_family(s), "random", s, f"train{s}")
+              for s in range(n_train)]
+    net = new_network(N, max_batch=4096, seed=seed)
+    t0 = time.perf_counter()
+    data = collect_samples(fac, bricks, net, n_iterates=n_iterates,
+                           elems_per_iterate=elems_per_iterate, seed=seed)
+    log(f"samples: {data.rows} rows from {data.meshes} meshes in {data.seconds:.1f} s")
+    t1 = time.perf_counter()
+    losses = train(net, data, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    tvar = float((data.T.double() ** 2).sum(1).mean() / net.n_out)
+    log(f"training: {epochs} epochs in {t_train:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}"
+        f" (target mean square {tvar:.4g})")
+    rows = data.rows
+    del data
+    trained = net.get_params()
+    vb = S.Brick(*train_dims, N, S.deformation_family(5000), "random", 5000, "val5000")
+    vf = torch.as_tensor(S.rhs_values(vb)).cuda()
+    val = {}
+    for a in dampings:
+        set_damping(net, trained, a)
+        r = evaluate(fac, vb, net, rtol=rtol, reps=1, f=vf)
+        val[a] = (r.learned_iters if not r.fell_back else 10 ** 9, r.jacobi_iters)
+        log(f"validation damping {a}: learned {r.learned_iters} it (fell back {r.fell_back} "
+            f"after {r.flexible_iters} flexible), Jacobi {r.jacobi_iters} it")
+    # the damping with the fewest validation iterations (ties: the larger);
+    # the learned preconditioner is deployed only if it beats Jacobi there
+    best = min(val, key=lambda a: (val[a][0], -a))
+    use_learned = val[best][0] < val[best][1]
+    set_damping(net, trained, best)
+    if eval_meshes is None:
+        eval_meshes = [S.Brick(32, 32, 32, N, S.deformation_family(10000), "random", 10000,
+                               "eval10000")]
+    results = []
+    for b in eval_meshes:
+        f = torch.as_tensor(S.rhs_values(b)).cuda() if b.rhs == "random" else None
+        r = evaluate(fac, b, net, rtol=rtol, reps=2, f=f)
+        log(f"eval {b.name} E={b.E}: Jacobi {r.jacobi_iters} it {r.jacobi_seconds:.3f} s, "
+            f"learned {r.learned_iters} it {r.learned_seconds:.3f} s, fell back {r.fell_back} "
+            f"after {r.flexible_iters} flexible")
+        results.append(r)
+    return {
+        "train_meshes": n_train, "train_dims": list(train_dims), "N": N,
+        "rows": rows, "sample_seconds": round(t1 - t0, 3), "train_seconds": round(t_train, 3),
+        "epochs": epochs, "loss_first": losses[0], "loss_last": losses[-1],
+        "target_mean_square": tvar,
+        "validation": {str(a): {"learned_iters": v[0] if v[0] < 10 ** 9 else None,
+                                "jacobi_iters": v[1]} for a, v in val.items()},
+        "damping": best, "learned_enabled": bool(use_learned),
+        "eval": [r.__dict__ for r in results],
+        "fallback_count": int(sum(r.fell_back for r in results)),
+    }
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="train and evaluate the learned preconditioner")
+    ap.add_argument("--train", type=int, default=16, help="number of training meshes")
+    ap.add_argument("--N", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--eval-n", type=int, default=32, help="held-out brick is n^3 elements")
+    args = ap.parse_args(argv)
+    import synthetic as S
+    ev = [S.Brick(args.eval_n, args.eval_n, args.eval_n, args.N, S.deformation_family(10000),
+                  "random", 10000, "eval10000")]
+    out = run_c5(n_train=args.train, N=args.N, epochs=args.epochs, eval_meshes=ev,
+                 log=lambda m: print(m, flush=True))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
