@@ -148,6 +148,34 @@ def main():
         del src, dst
         log(f"copy: {copy_gbs:.0f} GB/s")
 
+        # ---- reduced-precision AX variants (the mixed solve's inner operator)
+        variants = {}
+        u32 = u.float()
+        w32 = torch.empty_like(u32)
+        G32 = G.float()
+        runs = {"fp32": (lambda: nbx.ax(u32, G32, D, out=w32), 32)}
+        G16f, gsf = nbx.g16_pack(G, N, nbx.F16)
+        G16b, gsb = nbx.g16_pack(G, N, nbx.BF16)
+        runs["g_fp16"] = (lambda: nbx.ax_g16(u32, G16f, gsf, D, nbx.F16, out=w32), 20)
+        runs["g_bf16"] = (lambda: nbx.ax_g16(u32, G16b, gsb, D, nbx.BF16, out=w32), 20)
+        for name, (fn, bpn) in runs.items():
+            for _ in range(50):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(200):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / 200
+            gbs = bpn * E * N ** 3 / t / 1e9
+            variants[name] = {"mean_launch_us": round(t * 1e6, 2), "bytes_per_node": bpn,
+                              "achieved_gbs": round(gbs, 1),
+                              "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "gflops": round(flops / t / 1e9, 1)}
+            log(f"AX {name}: {t*1e6:.1f} us, {gbs:.0f} GB/s")
+        del u32, w32, G32, G16f, gsf, G16b, gsb
+
     ax_hash = src_hash("ax_kernel.hpp", "ax_f64.hip", "ax.hip")
     achieved = abytes / mean_launch / 1e9
     tb = traffic_record(ax_hash) if (N, E) == (10, 32768) else None
@@ -180,6 +208,7 @@ def main():
                      "median_launch_us": round(statistics.median(per) * 1e6, 2),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "ax_reduced_precision": variants,
     })
     del u, w, G, bm
     torch.cuda.empty_cache()
@@ -205,15 +234,19 @@ def main():
             _, r100 = st.problem.pcg(st.b, max_iter=100, fixed_iters=1, check_every=20)
             pcg["fp64_100_iterations_seconds"] = round(r100.seconds, 5)
             pcg["ms_per_iteration"] = round(r100.seconds / 100 * 1e3, 4)
-            variants = {"mixed_fp32": dict(mixed_mode=0, inner_rtol=0.1),
-                        "mixed_fp32_restarted": dict(mixed_mode=1, inner_rtol=1e-5)}
+            variants = {"mixed_fp32": dict(prec=nbx.F32, mixed_mode=0, inner_rtol=0.1),
+                        "mixed_fp32_restarted": dict(prec=nbx.F32, mixed_mode=1,
+                                                     inner_rtol=1e-5),
+                        "mixed_f16_storage": dict(prec=nbx.F16, mixed_mode=0, inner_rtol=0.1),
+                        "mixed_bf16_storage": dict(prec=nbx.BF16, mixed_mode=0,
+                                                   inner_rtol=0.1)}
             for name, kw in variants.items():
                 try:
                     times = []
                     for _ in range(3):
                         h0 = time.perf_counter()
                         xm, rm = st.problem.pcg(st.b, rtol=1e-10, max_iter=10000,
-                                                prec=nbx.F32, check_every=20, **kw)
+                                                check_every=20, **kw)
                         times.append(time.perf_counter() - h0)
                     err = float((xm - x64).abs().max() / x64.abs().max())
                     pcg[name] = {"iters": rm.iters, "outer": rm.outer_iters,
@@ -221,7 +254,11 @@ def main():
                                  "true_relres": rm.true_relres, "fell_back": rm.fell_back,
                                  "err_vs_fp64": err, "status": rm.status,
                                  "speedup_vs_fp64": round(pcg["fp64"]["seconds"] / min(times),
-                                                          3), **kw}
+                                                          3),
+                                 "inner": {nbx.F32: "fp32", nbx.F16: "G in fp16, fp32 vectors",
+                                           nbx.BF16: "G in bf16, fp32 vectors"}[kw["prec"]],
+                                 "mixed_mode": kw["mixed_mode"],
+                                 "inner_rtol": kw["inner_rtol"]}
                     log(f"{name}: {rm.iters} it / {rm.outer_iters} outer, {min(times):.4f} s")
                 except nbx.NbxError as e:
                     pcg[name] = {"unavailable": str(e)}

@@ -120,6 +120,27 @@ int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N,
 int nbx_ax_set_tile(int prec, int N, int epb);
 int nbx_ax_get_tile(int prec, int N);
 
+/* The reduced-storage operator for the inner iterations of a mixed-
+ * precision solve.  Half precision and fixed point are the paper's further
+ * work (Section V); G is 48 of AX's 64 bytes per node in FP64.
+ *
+ * nbx_g16_pack: per element e, gscale[e] = 2^(floor(log2 m_e) - 14) with
+ * m_e = max |G_e| (1 if G_e is zero), and G16[e][f][q] = the 16-bit word of
+ * round(round32(G[e][f][q] / gscale[e])), both roundings to nearest-even,
+ * first to FP32, then to gprec = NBX_F16 (IEEE binary16) or NBX_BF16
+ * (bfloat16).  G (FP64, [E][6][N^3]), G16 ([E][6][N^3] 16-bit words) and
+ * gscale ([E] float) are device arrays.  Async.
+ *
+ * nbx_ax_g16: w = AX(u) in FP32 arithmetic with the factors
+ * gscale[e] * G16_e (u, w float [E][N^3]); bit-identical to FP32 AX with
+ * those dequantised factors.  Async; tiles as nbx_ax with NBX_F32.
+ * Both: NBX_EINVAL for null pointers, N outside [2,16], E < 0, u == w;
+ * NBX_EUNSUPPORTED for another gprec. */
+int nbx_g16_pack(int gprec, const double *G, int N, int64_t E, void *G16, float *gscale,
+                 void *stream);
+int nbx_ax_g16(int gprec, const float *u, const void *G16, const float *gscale,
+               const double *D, int N, int64_t E, float *w, void *stream);
+
 /* ------------------------------------------------ gather-scatter (dssum) --
  * The "nearest-neighbour communication" step of a CG iteration (Section
  * II-B), on one GPU: local copies of a global node are summed and the sum
@@ -207,7 +228,9 @@ typedef struct {
     int use_graph;       /* nonzero: replay iterations from a captured hipGraph */
     double rtol;         /* stop when ||r||_c <= rtol ||b||_c */
     int prec;            /* NBX_F64: plain FP64 PCG; NBX_F32: FP32 iteration
-                            with FP64 residuals (see mixed_mode) */
+                            with FP64 residuals (see mixed_mode);
+                            NBX_F16 / NBX_BF16: the same with the inner
+                            operator's G in 16 bits (nbx_g16_pack) */
     double inner_rtol;   /* mixed_mode 0: residual reduction per reliable
                             update (e.g. 0.1); mixed_mode 1: relative
                             tolerance of each inner solve (e.g. 1e-5) */

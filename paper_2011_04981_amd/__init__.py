@@ -97,6 +97,8 @@ def lib():
         "nbx_mlp_forward": ([vp, vp, i32, vp, vp], i32),
         "nbx_mlp_grad": ([vp, vp, vp, i32, vp, vp], i32),
         "nbx_mlp_train_step": ([vp, vp, vp, i32, C.c_float, vp, vp], i32),
+        "nbx_g16_pack": ([i32, vp, i32, i64, vp, vp, vp], i32),
+        "nbx_ax_g16": ([i32, vp, vp, vp, vp, i32, i64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -245,6 +247,35 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[in
         _check(lib().nbx_ax_tiled(prec, _dptr(u, name="u"), _dptr(G, name="G"),
                                   _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
                                   int(epb), _stream(stream)), "nbx_ax_tiled")
+    return w
+
+
+def g16_pack(G, N: int, gprec: int, stream=None):
+    """(G16 [E, 6, N^3] int16 words, gscale [E] float32): the factors in
+    16-bit storage (gprec F16 or BF16) with per-element power-of-two
+    scales (nbx_g16_pack)."""
+    torch = _torch()
+    E = G.numel() // (6 * N ** 3)
+    G16 = torch.empty((E, 6, N ** 3), dtype=torch.int16, device=G.device)
+    gs = torch.empty(E, dtype=torch.float32, device=G.device)
+    _check(lib().nbx_g16_pack(gprec, _dptr(G, torch.float64, "G"), N, E, _dptr(G16),
+                              _dptr(gs), _stream(stream)), "nbx_g16_pack")
+    return G16, gs
+
+
+def ax_g16(u, G16, gscale, D, gprec: int, out=None, stream=None):
+    """w = AX(u) in FP32 with 16-bit factors (nbx_ax_g16)."""
+    torch = _torch()
+    N = D.shape[0]
+    E = u.numel() // N ** 3
+    if u.numel() != E * N ** 3 or G16.numel() != 6 * u.numel() or gscale.numel() != E:
+        raise ValueError("u [E, N^3], G16 [E, 6, N^3] and gscale [E] must agree")
+    w = torch.empty_like(u) if out is None else out
+    if w.numel() != u.numel():
+        raise ValueError("out must match u")
+    _check(lib().nbx_ax_g16(gprec, _dptr(u, torch.float32, "u"), _dptr(G16, torch.int16, "G16"),
+                            _dptr(gscale, torch.float32, "gscale"), _dptr(D, torch.float64, "D"),
+                            N, E, _dptr(w, torch.float32, "w"), _stream(stream)), "nbx_ax_g16")
     return w
 
 

@@ -1,8 +1,8 @@
 // ax.hip -- C-ABI front end of the AX operator (Section II-B, Listing 1):
 // argument checks, the per-(precision, N) tile table that the autotuner
 // fills, and the launch wrappers the solvers use.  The kernel itself is in
-// ax_kernel.hpp; its instantiations are in ax_f64.hip, ax_f32.hip and
-// ax_pcg.hip so that they compile in parallel.
+// ax_kernel.hpp; its instantiations are in ax_f64.hip, ax_f32.hip,
+// ax_pcg.hip, ax_f16.hip and ax_bf16.hip so that they compile in parallel.
 #include "internal.hpp"
 
 #include <atomic>
@@ -19,6 +19,16 @@ int ax_pcg_launch_f64_tiled(int N, int epb, const double *G, const double *D, in
 int ax_pcg_launch_f32_tiled(int N, int epb, const float *G, const double *D, int64_t E,
                             const float *z, float *p, float *w, double *part,
                             const double *scal, hipStream_t s);
+int ax_launch_g_f16(int N, int epb, const float *u, const void *G, const float *gscale,
+                    const double *D, float *w, int64_t E, hipStream_t s);
+int ax_launch_g_bf16(int N, int epb, const float *u, const void *G, const float *gscale,
+                     const double *D, float *w, int64_t E, hipStream_t s);
+int ax_pcg_launch_g_f16(int N, int epb, const void *G, const float *gscale, const double *D,
+                        int64_t E, const float *z, float *p, float *w, double *part,
+                        const double *scal, hipStream_t s);
+int ax_pcg_launch_g_bf16(int N, int epb, const void *G, const float *gscale, const double *D,
+                         int64_t E, const float *z, float *p, float *w, double *part,
+                         const double *scal, hipStream_t s);
 
 namespace {
 
@@ -46,7 +56,7 @@ bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4; }
 int ax_tile(int prec, int N)
 {
     init_tiles();
-    return g_tile[prec == NBX_F32 ? 1 : 0][N].load();
+    return g_tile[prec == NBX_F64 ? 0 : 1][N].load();   // FP32 arithmetic: one table
 }
 
 int ax_blocks(int prec, int N, int64_t E)
@@ -77,6 +87,24 @@ int ax_pcg_launch_f32(const float *G, const double *D, int N, int64_t E, const f
                       float *p, float *w, double *part, const double *scal, hipStream_t s)
 {
     return ax_pcg_launch_f32_tiled(N, ax_tile(NBX_F32, N), G, D, E, z, p, w, part, scal, s);
+}
+
+int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscale,
+                  const double *D, int N, int64_t E, float *w, hipStream_t s)
+{
+    const int epb = ax_tile(NBX_F32, N);
+    return gprec == NBX_F16 ? ax_launch_g_f16(N, epb, u, G16, gscale, D, w, E, s)
+                            : ax_launch_g_bf16(N, epb, u, G16, gscale, D, w, E, s);
+}
+
+int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const double *D, int N,
+                      int64_t E, const float *z, float *p, float *w, double *part,
+                      const double *scal, hipStream_t s)
+{
+    const int epb = ax_tile(NBX_F32, N);
+    return gprec == NBX_F16
+               ? ax_pcg_launch_g_f16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s)
+               : ax_pcg_launch_g_bf16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s);
 }
 
 }  // namespace nbx

@@ -23,6 +23,8 @@
 
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace nbx {
 
 template <int N, int EPB>
@@ -58,6 +60,25 @@ __device__ inline double ax_wave_sum(double v)
 
 template <typename T>
 __device__ inline T ax_ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+
+// Half-precision storage of the geometric factors (16-bit words holding
+// FP16 or BF16 bits), widened to FP32 on load.
+struct g_f16 { uint16_t bits; };
+struct g_bf16 { uint16_t bits; };
+
+template <typename T, typename GT>
+__device__ inline T ax_ldg(const GT *p)
+{
+    if constexpr (std::is_same<GT, g_f16>::value) {
+        const uint16_t b = __builtin_nontemporal_load(&p->bits);
+        return (T)(float)__builtin_bit_cast(_Float16, b);
+    } else if constexpr (std::is_same<GT, g_bf16>::value) {
+        const uint16_t b = __builtin_nontemporal_load(&p->bits);
+        return (T)__uint_as_float((uint32_t)b << 16);
+    } else {
+        return (T)__builtin_nontemporal_load(p);
+    }
+}
 template <typename T>
 __device__ inline void ax_st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 // Fused multiply-add written out: every instantiation (tile, fused or not)
@@ -72,11 +93,16 @@ __device__ inline float ax_fma(float a, float b, float c) { return __builtin_fma
 // blk selects the block's elements [blk*EPB, blk*EPB + EPB) of this
 // operator instance (blockIdx.x for a single operator; a table entry when
 // one launch serves several independent problems).
-template <typename T, int N, int EPB, bool PCG>
+// GT is the storage type of G (T, or g_f16 / g_bf16 with T = float); for
+// 16-bit storage G_e holds G_e / gscale[e] (gscale[e] a power of two) and
+// the element's result is multiplied by gscale[e], which in FP32 is exact
+// and commutes with every rounding of the element's arithmetic.
+template <typename T, int N, int EPB, bool PCG, typename GT = T>
 __device__ __forceinline__ void
-ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
+ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__restrict__ Dg,
         T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
-        const double *__restrict__ scal, int64_t E, int64_t blk)
+        const double *__restrict__ scal, int64_t E, int64_t blk,
+        const float *__restrict__ gscale = nullptr)
 {
 #pragma clang fp contract(off)
     using S = AxShape<N, EPB>;
@@ -100,7 +126,8 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
     const bool valid = lane_act && e_raw < E;  // ragged last block
     const int64_t e = e_raw < E ? e_raw : E - 1;
     const size_t base = (size_t)e * N3;
-    const T *Ge = G + (size_t)e * 6 * N3;
+    const GT *Ge = G + (size_t)e * 6 * N3;
+    constexpr bool kHalfG = !std::is_same<GT, T>::value;
     T *su = s_u + el * N3, *swr = s_wr + el * N3, *sws = s_ws + el * N3;
 
     // 1. the column of u (or of z and the previous p) first ...
@@ -125,7 +152,7 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
-        for (int k = 0; k < PF; ++k) g[f][k] = ax_ld_nt(Ge + f * N3 + k * N2 + tc);
+        for (int k = 0; k < PF; ++k) g[f][k] = ax_ldg<T>(Ge + f * N3 + k * N2 + tc);
     for (int q = t; q < N2; q += NT) s_D[q] = (T)Dg[q];
     if constexpr (PCG) {
         if (valid) {
@@ -159,9 +186,10 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
             if (k < PF) {
                 g1 = g[0][k]; g2 = g[1][k]; g3 = g[2][k]; g4 = g[3][k]; g5 = g[4][k]; g6 = g[5][k];
             } else {
-                const T *gp = Ge + k * N2 + tc;
-                g1 = ax_ld_nt(gp); g2 = ax_ld_nt(gp + N3); g3 = ax_ld_nt(gp + 2 * N3);
-                g4 = ax_ld_nt(gp + 3 * N3); g5 = ax_ld_nt(gp + 4 * N3); g6 = ax_ld_nt(gp + 5 * N3);
+                const GT *gp = Ge + k * N2 + tc;
+                g1 = ax_ldg<T>(gp); g2 = ax_ldg<T>(gp + N3); g3 = ax_ldg<T>(gp + 2 * N3);
+                g4 = ax_ldg<T>(gp + 3 * N3); g5 = ax_ldg<T>(gp + 4 * N3);
+                g6 = ax_ldg<T>(gp + 5 * N3);
             }
             const T wr = ax_fma(g3, ut, ax_fma(g2, us, g1 * ur));
             const T ws = ax_fma(g5, ut, ax_fma(g4, us, g2 * ur));
@@ -173,6 +201,8 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
 
     // 4. local_grad3_t: w = D^T wr + (ws D per slab) + wt D
     double pw = 0.0;
+    T gsc = (T)1;
+    if constexpr (kHalfG) gsc = (T)gscale[e];
     {
         T DTi[N], DTj[N];
 #pragma unroll
@@ -187,6 +217,7 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
 #pragma unroll
             for (int m = 0; m < N; ++m)
                 acc = ax_fma(kDLds ? s_D[m * N + k] : (T)Dg[m * N + k], wt[m], acc);
+            if constexpr (kHalfG) acc *= gsc;
             if (valid) ax_st_nt(acc, w + base + k * N2 + tc);
             if constexpr (PCG) pw += (double)uc[k] * (double)acc;
         }
@@ -205,29 +236,29 @@ ax_body(const T *__restrict__ uin, const T *__restrict__ G, const double *__rest
     }
 }
 
-template <typename T, int N, int EPB, bool PCG>
+template <typename T, int N, int EPB, bool PCG, typename GT = T>
 __global__ void __launch_bounds__((AxShape<N, EPB>::NT))
-ax_kernel(const T *__restrict__ uin, const T *__restrict__ G, const double *__restrict__ Dg,
+ax_kernel(const T *__restrict__ uin, const GT *__restrict__ G, const double *__restrict__ Dg,
           T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
-          const double *__restrict__ scal, int64_t E)
+          const double *__restrict__ scal, int64_t E, const float *__restrict__ gscale)
 {
-    ax_body<T, N, EPB, PCG>(uin, G, Dg, w, pio, part, scal, E, (int64_t)blockIdx.x);
+    ax_body<T, N, EPB, PCG, GT>(uin, G, Dg, w, pio, part, scal, E, (int64_t)blockIdx.x, gscale);
 }
 
 // Elements per workgroup the library may use (the autotuner's search space).
 constexpr int kEpbChoices[] = {1, 2, 4};
 
-template <typename T, bool PCG, int N>
-int ax_launch_epb(int epb, const T *u, const T *G, const double *D, T *w, T *p, double *part,
-                  const double *scal, int64_t E, hipStream_t s)
+template <typename T, bool PCG, int N, typename GT = T>
+int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p, double *part,
+                  const double *scal, int64_t E, hipStream_t s, const float *gscale = nullptr)
 {
 #define NBX_EPB_CASE(EE)                                                                     \
     case EE: {                                                                               \
         if constexpr (AxShape<N, EE>::template fits<T>()) {                                  \
             constexpr int NT_ = AxShape<N, EE>::NT;                                          \
             const int64_t nb = (E + EE - 1) / EE;                                            \
-            hipLaunchKernelGGL((ax_kernel<T, N, EE, PCG>), dim3((unsigned)nb), dim3(NT_), 0, \
-                               s, u, G, D, w, p, part, scal, E);                             \
+            hipLaunchKernelGGL((ax_kernel<T, N, EE, PCG, GT>), dim3((unsigned)nb), dim3(NT_), \
+                               0, s, u, G, D, w, p, part, scal, E, gscale);                  \
             return NBX_OK;                                                                   \
         } else {                                                                             \
             return NBX_EUNSUPPORTED;                                                         \
@@ -242,15 +273,18 @@ int ax_launch_epb(int epb, const T *u, const T *G, const double *D, T *w, T *p, 
 #undef NBX_EPB_CASE
 }
 
-template <typename T, bool PCG>
-int ax_launch_any(int N, int epb, const T *u, const T *G, const double *D, T *w, T *p,
-                  double *part, const double *scal, int64_t E, hipStream_t s)
+template <typename T, bool PCG, typename GT = T>
+int ax_launch_any(int N, int epb, const T *u, const GT *G, const double *D, T *w, T *p,
+                  double *part, const double *scal, int64_t E, hipStream_t s,
+                  const float *gscale = nullptr)
 {
     if (E <= 0) return NBX_OK;
     if ((E + epb - 1) / epb > 0x7fffffffLL) return NBX_EUNSUPPORTED;
     int st;
 #define NBX_N_CASE(NN)                                                                     \
-    case NN: st = ax_launch_epb<T, PCG, NN>(epb, u, G, D, w, p, part, scal, E, s); break;
+    case NN:                                                                               \
+        st = ax_launch_epb<T, PCG, NN, GT>(epb, u, G, D, w, p, part, scal, E, s, gscale);  \
+        break;
     switch (N) {
         NBX_N_CASE(2) NBX_N_CASE(3) NBX_N_CASE(4) NBX_N_CASE(5) NBX_N_CASE(6)
         NBX_N_CASE(7) NBX_N_CASE(8) NBX_N_CASE(9) NBX_N_CASE(10) NBX_N_CASE(11)

@@ -62,6 +62,13 @@ int ax_pcg_launch_f64(const double *G, const double *D, int N, int64_t E, const 
                       double *p, double *w, double *part, const double *scal, hipStream_t s);
 int ax_pcg_launch_f32(const float *G, const double *D, int N, int64_t E, const float *z,
                       float *p, float *w, double *part, const double *scal, hipStream_t s);
+// AX with 16-bit geometric factors (gprec NBX_F16 or NBX_BF16; G16 holds
+// G_e / gscale[e]) on FP32 vectors, plain and fused; tiles as for NBX_F32.
+int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscale,
+                  const double *D, int N, int64_t E, float *w, hipStream_t s);
+int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const double *D, int N,
+                      int64_t E, const float *z, float *p, float *w, double *part,
+                      const double *scal, hipStream_t s);
 // Elements per workgroup currently selected for (prec, N), and the
 // resulting number of AX workgroups for E elements.
 int ax_tile(int prec, int N);

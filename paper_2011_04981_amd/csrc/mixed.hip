@@ -57,8 +57,11 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
     const int nb1 = ax_blocks(NBX_F32, P->N, P->E);
     const int nb3 = sk::red_blocks(P->n);
     for (int it = 0; it < n_iter; ++it) {
-        int st = ax_pcg_launch_f32(P->G32, P->D, P->N, P->E, P->z32, P->p32, P->w32, P->part1,
-                                   P->scal32, s);
+        int st = P->inner_fmt == NBX_F32
+                     ? ax_pcg_launch_f32(P->G32, P->D, P->N, P->E, P->z32, P->p32, P->w32,
+                                         P->part1, P->scal32, s)
+                     : ax_pcg_launch_g16(P->inner_fmt, P->G16, P->gscale, P->D, P->N, P->E,
+                                         P->z32, P->p32, P->w32, P->part1, P->scal32, s);
         if (st != NBX_OK) return st;
         hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, P->part1,
                            P->scal32);
@@ -76,29 +79,48 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
 
 }  // namespace
 
-int prepare_f32(nbx_problem *P, hipStream_t s)
+int prepare_inner(nbx_problem *P, int fmt, hipStream_t s)
 {
-    if (P->G32) return NBX_OK;
+    if (fmt != NBX_F32 && fmt != NBX_F16 && fmt != NBX_BF16) return NBX_EUNSUPPORTED;
     const size_t n = (size_t)P->n;
-    if (hipMalloc(&P->G32, 6 * n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->dinv32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->r32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->z32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->p32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->w32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->d32, n * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->scal32, NBX_SCAL_LEN * sizeof(double)) != hipSuccess) {
-        hipFree(P->G32); hipFree(P->dinv32); hipFree(P->r32); hipFree(P->z32);
-        hipFree(P->p32); hipFree(P->w32); hipFree(P->d32); hipFree(P->scal32);
-        P->G32 = P->dinv32 = P->r32 = P->z32 = P->p32 = P->w32 = P->d32 = nullptr;
-        P->scal32 = nullptr;
-        return NBX_ENOMEM;
+    if (!P->dinv32) {
+        if (hipMalloc(&P->dinv32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->r32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->z32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->p32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->w32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->d32, n * sizeof(float)) != hipSuccess ||
+            hipMalloc(&P->scal32, NBX_SCAL_LEN * sizeof(double)) != hipSuccess) {
+            hipFree(P->dinv32); hipFree(P->r32); hipFree(P->z32); hipFree(P->p32);
+            hipFree(P->w32); hipFree(P->d32); hipFree(P->scal32);
+            P->dinv32 = P->r32 = P->z32 = P->p32 = P->w32 = P->d32 = nullptr;
+            P->scal32 = nullptr;
+            return NBX_ENOMEM;
+        }
+        hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n,
+                           P->dinv, P->dinv32);
+        NBX_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(6 * P->n)), dim3(256), 0, s, 6 * P->n,
-                       P->G, P->G32);
-    hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n, P->dinv,
-                       P->dinv32);
-    NBX_LAUNCH_CHECK();
+    if (fmt == NBX_F32 && !P->G32) {
+        if (hipMalloc(&P->G32, 6 * n * sizeof(float)) != hipSuccess) return NBX_ENOMEM;
+        hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(6 * P->n)), dim3(256), 0, s,
+                           6 * P->n, P->G, P->G32);
+        NBX_LAUNCH_CHECK();
+    }
+    if (fmt != NBX_F32 && P->g16_fmt != fmt) {
+        if (!P->G16) {
+            if (hipMalloc(&P->G16, 6 * n * sizeof(uint16_t)) != hipSuccess) return NBX_ENOMEM;
+            if (hipMalloc(&P->gscale, (size_t)P->E * sizeof(float)) != hipSuccess) {
+                hipFree(P->G16);
+                P->G16 = nullptr;
+                return NBX_ENOMEM;
+            }
+        }
+        int st = nbx_g16_pack(fmt, P->G, P->N, P->E, P->G16, P->gscale, s);
+        if (st != NBX_OK) return st;
+        P->g16_fmt = fmt;
+    }
+    P->inner_fmt = fmt;
     NBX_HIP(hipStreamSynchronize(s));
     return NBX_OK;
 }
@@ -117,7 +139,8 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
                        P->scal32, o.inner_rtol, 0, max_iter);
     NBX_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk)) {
+    if (o.use_graph &&
+        (P->gexec32 == nullptr || P->g32_iters != chunk || P->g32_fmt != P->inner_fmt)) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -130,6 +153,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
         hipGraphDestroy(g);
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
+        P->g32_fmt = P->inner_fmt;
     }
     int done = 0;
     while (true) {
@@ -257,13 +281,14 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
                               const nbx_pcg_opts &o, nbx_pcg_result *res)
 {
     hipStream_t s = P->ws;
-    int st = prepare_f32(P, s);
+    int st = prepare_inner(P, o.prec, s);
     if (st != NBX_OK) return st;
     const GsPlan &gs = P->gs->plan;
     const int nb = sk::red_blocks(P->n);
     const double delta = (o.inner_rtol > 0 && o.inner_rtol < 1) ? o.inner_rtol : 0.1;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk)) {
+    if (o.use_graph &&
+        (P->gexec32 == nullptr || P->g32_iters != chunk || P->g32_fmt != P->inner_fmt)) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -276,6 +301,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
         hipGraphDestroy(g);
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
+        P->g32_fmt = P->inner_fmt;
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
@@ -387,7 +413,7 @@ static int pcg_mixed_restart(nbx_problem *P, const double *b, double *x,
                              const nbx_pcg_opts &o, nbx_pcg_result *res)
 {
     hipStream_t s = P->ws;
-    int st = prepare_f32(P, s);
+    int st = prepare_inner(P, o.prec, s);
     if (st != NBX_OK) return st;
     const auto t0 = std::chrono::steady_clock::now();
     // x = 0, r = b, ||b||_c

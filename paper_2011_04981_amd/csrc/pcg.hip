@@ -178,7 +178,7 @@ extern "C" int nbx_problem_destroy(nbx_problem *P)
     hipFree(P->dinv); hipFree(P->r); hipFree(P->z); hipFree(P->p); hipFree(P->w);
     hipFree(P->part1); hipFree(P->part3); hipFree(P->scal); hipFree(P->tmp2);
     hipFree(P->G32); hipFree(P->dinv32); hipFree(P->r32); hipFree(P->z32); hipFree(P->p32);
-    hipFree(P->w32); hipFree(P->d32); hipFree(P->scal32);
+    hipFree(P->w32); hipFree(P->d32); hipFree(P->scal32); hipFree(P->G16); hipFree(P->gscale);
     if (P->h_scal) hipHostFree(P->h_scal);
     if (P->ev) hipEventDestroy(P->ev);
     if (P->ws) hipStreamDestroy(P->ws);
@@ -229,7 +229,8 @@ extern "C" int nbx_pcg(nbx_problem *P, const double *b, double *x, const nbx_pcg
     NBX_HIP(hipStreamWaitEvent(P->ws, P->ev, 0));
     int st;
     if (o.prec == NBX_F64) st = pcg_f64(P, b, x, o, res);
-    else if (o.prec == NBX_F32) st = pcg_mixed(P, b, x, o, res);
+    else if (o.prec == NBX_F32 || o.prec == NBX_F16 || o.prec == NBX_BF16)
+        st = pcg_mixed(P, b, x, o, res);
     else return NBX_EUNSUPPORTED;
     if (st != NBX_OK) return st;
     NBX_HIP(hipEventRecord(P->ev, P->ws));

@@ -23,7 +23,12 @@ struct nbx_problem {
           *w32 = nullptr, *d32 = nullptr;
     double *scal32 = nullptr;
     hipGraphExec_t gexec32 = nullptr;
-    int g32_iters = 0;
+    int g32_iters = 0, g32_fmt = -1;   // chunk and inner format the graph was captured with
+    // 16-bit factors for the reduced-storage inner operator (NBX_F16 / NBX_BF16)
+    uint16_t *G16 = nullptr;
+    float *gscale = nullptr;
+    int g16_fmt = -1;                  // format G16 currently holds
+    int inner_fmt = NBX_F32;           // operator the FP32 iterations use
 };
 
 namespace nbx {
@@ -37,6 +42,9 @@ int pcg_f64(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
             nbx_pcg_result *res);
 int pcg_mixed(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
               nbx_pcg_result *res);
-int prepare_f32(nbx_problem *P, hipStream_t s);
+// FP32 inner workspace and the inner operator's factors in format fmt
+// (NBX_F32: FP32 copy of G; NBX_F16 / NBX_BF16: 16-bit packed G); sets
+// P->inner_fmt.  Synchronous.
+int prepare_inner(nbx_problem *P, int fmt, hipStream_t s);
 
 }  // namespace nbx
