@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--N", type=int, default=10, help="GLL nodes per direction")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solve leg")
     ap.add_argument("--nbatch", type=int, default=64, help="problems in the batched leg")
+    ap.add_argument("--no-ax-variants", action="store_true",
+                    help="skip the FP32 and 16-bit-G AX timings")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner leg")
     ap.add_argument("--learned-train", type=int, default=8,
@@ -158,6 +160,8 @@ def main():
         G16b, gsb = nbx.g16_pack(G, N, nbx.BF16)
         runs["g_fp16"] = (lambda: nbx.ax_g16(u32, G16f, gsf, D, nbx.F16, out=w32), 20)
         runs["g_bf16"] = (lambda: nbx.ax_g16(u32, G16b, gsb, D, nbx.BF16, out=w32), 20)
+        if a.no_ax_variants:
+            runs = {}
         for name, (fn, bpn) in runs.items():
             for _ in range(50):
                 fn()
@@ -233,6 +237,8 @@ def main():
             x64 = x.clone()
             _, r100 = st.problem.pcg(st.b, max_iter=100, fixed_iters=1, check_every=20)
             pcg["fp64_100_iterations_seconds"] = round(r100.seconds, 5)
+            pcg["fused_stage_tile"] = {"f64": nbx.get_pcg_tile(nbx.F64, N),
+                                       "f32": nbx.get_pcg_tile(nbx.F32, N)}
             pcg["ms_per_iteration"] = round(r100.seconds / 100 * 1e3, 4)
             variants = {"mixed_fp32": dict(prec=nbx.F32, mixed_mode=0, inner_rtol=0.1),
                         "mixed_fp32_restarted": dict(prec=nbx.F32, mixed_mode=1,
@@ -301,7 +307,8 @@ def main():
                 "latency_p50_s": round(pct(0.50), 5), "latency_p99_s": round(pct(0.99), 5),
                 "latency_max_s": round(lat_sorted[-1], 5),
                 "iterations_min_max": [min(r.iters for r in res), max(r.iters for r in res)],
-                "tiles": {str(N): nbx.get_tile(nbx.F64, N) for N in (6, 8, 10, 12)}}
+                "fused_stage_tiles": {str(N): nbx.get_pcg_tile(nbx.F64, N)
+                                      for N in (6, 8, 10, 12)}}
             log(f"batched: {wall:.3f} s vs sequential {seq:.3f} s, "
                 f"p50 {pct(0.5):.4f} s p99 {pct(0.99):.4f} s")
             del sets, probs, bs, xs

@@ -115,10 +115,18 @@ int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64
 int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
                  void *w, int epb, void *stream);
 
-/* The tile nbx_ax and the solvers use for (prec, N) (process-wide; set by
- * the autotuner).  get returns epb or a negative status. */
+/* The tile nbx_ax uses for (prec, N) (process-wide; set by the
+ * autotuner).  get returns epb or a negative status.  prec NBX_F64 or
+ * NBX_F32 (the FP32 table also serves nbx_ax_g16). */
 int nbx_ax_set_tile(int prec, int N, int epb);
 int nbx_ax_get_tile(int prec, int N);
+/* The tile of the solvers' fused first stage (p = z + beta p, w = AX(p),
+ * per-workgroup <p,w> partials) for (prec, N): nbx_pcg, nbx_pcg_iterate,
+ * nbx_pcg_batched, nbx_pcg_learned.  The partials follow the workgroups, so
+ * a solve's rounding (not its correctness) depends on this tile; standalone
+ * and batched solves share it and agree bit for bit. */
+int nbx_pcg_set_tile(int prec, int N, int epb);
+int nbx_pcg_get_tile(int prec, int N);
 
 /* The reduced-storage operator for the inner iterations of a mixed-
  * precision solve.  Half precision and fixed point are the paper's further

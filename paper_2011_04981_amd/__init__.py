@@ -73,6 +73,8 @@ def lib():
         "nbx_ax_tiled": ([i32, vp, vp, vp, i32, i64, vp, i32, vp], i32),
         "nbx_ax_set_tile": ([i32, i32, i32], i32),
         "nbx_ax_get_tile": ([i32, i32], i32),
+        "nbx_pcg_set_tile": ([i32, i32, i32], i32),
+        "nbx_pcg_get_tile": ([i32, i32], i32),
         "nbx_gs_create": ([vp, vp, i64, C.POINTER(vp)], i32),
         "nbx_gs_destroy": ([vp], i32),
         "nbx_dssum": ([vp, i32, vp, i32, vp], i32),
@@ -119,11 +121,13 @@ def _apply_tile_cache(L) -> None:
     with open(path) as f:
         rec = json.load(f)
     for pname, rows in rec.get("tiles", {}).items():
-        prec = {"f64": F64, "f32": F32}.get(pname)
-        if prec is None:
+        kind, _, pn = pname.rpartition("_")
+        prec = {"f64": F64, "f32": F32}.get(pn)
+        setter = {"": L.nbx_ax_set_tile, "pcg": L.nbx_pcg_set_tile}.get(kind)
+        if prec is None or setter is None:
             continue
         for N, row in rows.items():
-            L.nbx_ax_set_tile(prec, int(N), int(row["epb"]))
+            setter(prec, int(N), int(row["epb"]))
 
 
 def _check(st: int, what: str) -> int:
@@ -285,6 +289,15 @@ def set_tile(prec: int, N: int, epb: int) -> None:
 
 def get_tile(prec: int, N: int) -> int:
     return _check(lib().nbx_ax_get_tile(prec, N), "nbx_ax_get_tile")
+
+
+def set_pcg_tile(prec: int, N: int, epb: int) -> None:
+    """Tile of the solvers' fused first stage (nbx_pcg_set_tile)."""
+    _check(lib().nbx_pcg_set_tile(prec, N, epb), "nbx_pcg_set_tile")
+
+
+def get_pcg_tile(prec: int, N: int) -> int:
+    return _check(lib().nbx_pcg_get_tile(prec, N), "nbx_pcg_get_tile")
 
 
 # --------------------------------------------------------- gather-scatter

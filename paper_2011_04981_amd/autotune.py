@@ -1,11 +1,15 @@
 """Tile autotuner for the AX kernel (elements per workgroup).
 
-For every (precision, N) it times each tile the library offers
-(nbx_ax_tiled with 1, 2 or 4 elements per workgroup) on an HBM-sized
-synthetic operator, keeps the fastest, installs it in the library's tile
-table (nbx_ax_set_tile, used by nbx_ax, the solvers and the batched solver)
-and can store the table as JSON.  Every tile computes identical bits, so the
-choice only affects speed.
+Two tables, both indexed by (precision, N):
+  * the plain operator (nbx_ax): each tile the library offers (nbx_ax_tiled
+    with 1, 2 or 4 elements per workgroup) is timed on an HBM-sized
+    synthetic operator; every tile computes identical bits;
+  * the solvers' fused first stage (p update, AX, <p,w> partials;
+    nbx_pcg_set_tile), whose register and LDS use differ: each tile is timed
+    as whole CG iterations on a deformed brick of the same size (FP64 Jacobi
+    PCG for "f64", the FP32 inner iterations of the mixed solve for "f32").
+The fastest tile is installed and the table can be stored as JSON, which
+the package applies when the library loads.
 
     python -m paper_2011_04981_amd.autotune --save   # writes tiles.json
 """
@@ -17,7 +21,7 @@ import os
 import statistics
 from typing import Dict, Iterable, Optional
 
-from . import F32, F64, NbxError, ax, lib, set_tile
+from . import F32, F64, NbxError, ax, get_pcg_tile, lib, set_pcg_tile, set_tile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tiles.json")
@@ -65,10 +69,55 @@ def time_tiles(prec: int, N: int, nodes: int = 16_000_000, reps: int = 20,
     return out
 
 
+def _brick_dims(E: int):
+    n = max(1, round(E ** (1 / 3)))
+    return n, n, max(1, E // (n * n))
+
+
+def time_pcg_tiles(prec: int, N: int, nodes: int = 8_000_000, iters: int = 60,
+                   seed: int = 0) -> Dict[int, float]:
+    """Seconds per CG iteration with each fused-stage tile on a deformed
+    brick of about `nodes` local nodes (best of two solves per tile)."""
+    import torch
+    from . import setup_brick
+    ex, ey, ez = _brick_dims(max(8, nodes // N ** 3))
+    d = [[0.05, 2, 2, 2]] * 3
+    st = setup_brick(ex, ey, ez, N, d)
+    out = {}
+    old = get_pcg_tile(prec, N)
+    for epb in TILES:
+        try:
+            set_pcg_tile(prec, N, epb)
+        except NbxError:
+            continue
+        best = None
+        for _ in range(2):
+            try:
+                if prec == F64:
+                    _, r = st.problem.pcg(st.b, max_iter=iters, fixed_iters=1, check_every=20)
+                else:
+                    _, r = st.problem.pcg(st.b, rtol=1e-6, max_iter=20 * iters, prec=F32,
+                                          check_every=20)
+            except NbxError as e:
+                if e.status == -2:
+                    break
+                raise
+            per = r.seconds / max(r.iters, 1)
+            best = per if best is None else min(best, per)
+        if best is not None:
+            out[epb] = best
+    set_pcg_tile(prec, N, old)
+    st.problem.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def tune(Ns: Iterable[int] = (6, 8, 10, 12), precs: Iterable[int] = (F64, F32),
-         nodes: int = 16_000_000, reps: int = 20, apply: bool = True) -> dict:
+         nodes: int = 16_000_000, reps: int = 20, apply: bool = True,
+         pcg: bool = True) -> dict:
     """Times every tile for every (precision, N), installs the fastest and
-    returns {"f64": {"10": {"epb": 2, "us": {"1": .., "2": .., "4": ..}}}, ...}."""
+    returns {"f64": {"10": {"epb": 2, "us": {"1": .., "2": .., "4": ..}}},
+    "pcg_f64": {...}, ...} (pcg_* rows: microseconds per CG iteration)."""
     table: dict = {}
     for prec in precs:
         for N in Ns:
@@ -78,6 +127,13 @@ def tune(Ns: Iterable[int] = (6, 8, 10, 12), precs: Iterable[int] = (F64, F32),
                 "epb": best, "us": {str(k): round(v * 1e6, 2) for k, v in t.items()}}
             if apply:
                 set_tile(prec, N, best)
+            if pcg:
+                t = time_pcg_tiles(prec, N, nodes=nodes // 2)
+                best = min(t, key=t.get)
+                table.setdefault("pcg_" + PREC_NAME[prec], {})[str(N)] = {
+                    "epb": best, "us": {str(k): round(v * 1e6, 2) for k, v in t.items()}}
+                if apply:
+                    set_pcg_tile(prec, N, best)
     return table
 
 
@@ -85,11 +141,13 @@ def apply_table(table: dict) -> int:
     """Installs a stored table; returns the number of entries applied."""
     n = 0
     for pname, rows in table.items():
-        prec = {v: k for k, v in PREC_NAME.items()}.get(pname)
-        if prec is None:
+        kind, _, pn = pname.rpartition("_")
+        prec = {v: k for k, v in PREC_NAME.items()}.get(pn)
+        setter = {"": set_tile, "pcg": set_pcg_tile}.get(kind)
+        if prec is None or setter is None:
             continue
         for N, row in rows.items():
-            set_tile(prec, int(N), int(row["epb"]))
+            setter(prec, int(N), int(row["epb"]))
             n += 1
     return n
 
@@ -119,8 +177,9 @@ def main():
     ap.add_argument("--N", type=int, nargs="*", default=[6, 8, 10, 12])
     ap.add_argument("--nodes", type=int, default=16_000_000)
     ap.add_argument("--save", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the fused-stage table")
     a = ap.parse_args()
-    table = tune(a.N, nodes=a.nodes)
+    table = tune(a.N, nodes=a.nodes, pcg=not a.no_pcg)
     print(json.dumps(table, indent=1))
     if a.save:
         print("saved", save(table))

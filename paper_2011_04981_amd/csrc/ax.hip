@@ -32,22 +32,27 @@ int ax_pcg_launch_g_bf16(int N, int epb, const void *G, const float *gscale, con
 
 namespace {
 
-// Elements per workgroup by [precision][N].  Defaults: two elements per
-// block where a block's three LDS slabs stay small (measured best at
-// N = 10 in FP64), one for the large elements.
-std::atomic<int> g_tile[2][kMaxN + 1];
+// Elements per workgroup by [kind][precision][N]; kind 0 is the plain
+// operator (nbx_ax), kind 1 the solvers' fused first stage (p update, AX,
+// <p,w> partials), whose register and LDS use differ.  Defaults: two
+// elements per block where a block's three LDS slabs stay small (measured
+// best at N = 10 in FP64), one for the large elements.
+std::atomic<int> g_tile[2][2][kMaxN + 1];
 std::atomic<bool> g_tile_init{false};
 
 void init_tiles()
 {
     if (g_tile_init.load()) return;
-    for (int p = 0; p < 2; ++p)
-        for (int n = 0; n <= kMaxN; ++n) {
-            int e = n <= 6 ? 4 : (n <= 12 ? 2 : 1);
-            g_tile[p][n].store(e);
-        }
+    for (int k = 0; k < 2; ++k)
+        for (int p = 0; p < 2; ++p)
+            for (int n = 0; n <= kMaxN; ++n) {
+                int e = n <= 6 ? 4 : (n <= 12 ? 2 : 1);
+                g_tile[k][p][n].store(e);
+            }
     g_tile_init.store(true);
 }
+
+int prec_slot(int prec) { return prec == NBX_F64 ? 0 : 1; }   // FP32 arithmetic: one table
 
 bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4; }
 
@@ -56,12 +61,18 @@ bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4; }
 int ax_tile(int prec, int N)
 {
     init_tiles();
-    return g_tile[prec == NBX_F64 ? 0 : 1][N].load();   // FP32 arithmetic: one table
+    return g_tile[0][prec_slot(prec)][N].load();
+}
+
+int pcg_tile(int prec, int N)
+{
+    init_tiles();
+    return g_tile[1][prec_slot(prec)][N].load();
 }
 
 int ax_blocks(int prec, int N, int64_t E)
 {
-    const int epb = ax_tile(prec, N);
+    const int epb = pcg_tile(prec, N);
     return (int)((E + epb - 1) / epb);
 }
 
@@ -80,13 +91,13 @@ int ax_launch_f32(const float *u, const float *G, const double *D, int N, int64_
 int ax_pcg_launch_f64(const double *G, const double *D, int N, int64_t E, const double *z,
                       double *p, double *w, double *part, const double *scal, hipStream_t s)
 {
-    return ax_pcg_launch_f64_tiled(N, ax_tile(NBX_F64, N), G, D, E, z, p, w, part, scal, s);
+    return ax_pcg_launch_f64_tiled(N, pcg_tile(NBX_F64, N), G, D, E, z, p, w, part, scal, s);
 }
 
 int ax_pcg_launch_f32(const float *G, const double *D, int N, int64_t E, const float *z,
                       float *p, float *w, double *part, const double *scal, hipStream_t s)
 {
-    return ax_pcg_launch_f32_tiled(N, ax_tile(NBX_F32, N), G, D, E, z, p, w, part, scal, s);
+    return ax_pcg_launch_f32_tiled(N, pcg_tile(NBX_F32, N), G, D, E, z, p, w, part, scal, s);
 }
 
 int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscale,
@@ -101,7 +112,7 @@ int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const dou
                       int64_t E, const float *z, float *p, float *w, double *part,
                       const double *scal, hipStream_t s)
 {
-    const int epb = ax_tile(NBX_F32, N);
+    const int epb = pcg_tile(NBX_F32, N);
     return gprec == NBX_F16
                ? ax_pcg_launch_g_f16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s)
                : ax_pcg_launch_g_bf16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s);
@@ -145,18 +156,23 @@ extern "C" int nbx_ax_tiled(int prec, const void *u, const void *G, const double
     return ax_launch_f32_tiled(N, epb, (const float *)u, (const float *)G, D, (float *)w, E, s);
 }
 
-extern "C" int nbx_ax_set_tile(int prec, int N, int epb)
+static int set_tile(int kind, int prec, int N, int epb)
 {
     if (N < 2 || N > kMaxN || !valid_epb(epb)) return NBX_EINVAL;
     if (prec != NBX_F64 && prec != NBX_F32) return NBX_EUNSUPPORTED;
     init_tiles();
-    g_tile[prec == NBX_F32 ? 1 : 0][N].store(epb);
+    g_tile[kind][prec_slot(prec)][N].store(epb);
     return NBX_OK;
 }
 
-extern "C" int nbx_ax_get_tile(int prec, int N)
+static int get_tile(int kind, int prec, int N)
 {
     if (N < 2 || N > kMaxN) return NBX_EINVAL;
     if (prec != NBX_F64 && prec != NBX_F32) return NBX_EUNSUPPORTED;
-    return ax_tile(prec, N);
+    return kind == 0 ? ax_tile(prec, N) : pcg_tile(prec, N);
 }
+
+extern "C" int nbx_ax_set_tile(int prec, int N, int epb) { return set_tile(0, prec, N, epb); }
+extern "C" int nbx_ax_get_tile(int prec, int N) { return get_tile(0, prec, N); }
+extern "C" int nbx_pcg_set_tile(int prec, int N, int epb) { return set_tile(1, prec, N, epb); }
+extern "C" int nbx_pcg_get_tile(int prec, int N) { return get_tile(1, prec, N); }

@@ -250,7 +250,7 @@ extern "C" int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b
         for (int p = 0; p < nprob; ++p)
             if (probs[p]->N == N)
                 for (int q = 0; q < hd[p].nb1; ++q) ta.push_back({p, q});
-        BatchPlan::AxClass c{N, ax_tile(NBX_F64, N), (int)ta.size(), nullptr};
+        BatchPlan::AxClass c{N, pcg_tile(NBX_F64, N), (int)ta.size(), nullptr};
         if ((st = upload(&c.tab, ta)) != NBX_OK) return st;
         B.ax.push_back(c);
     }

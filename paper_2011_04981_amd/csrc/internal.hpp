@@ -69,9 +69,11 @@ int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscal
 int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const double *D, int N,
                       int64_t E, const float *z, float *p, float *w, double *part,
                       const double *scal, hipStream_t s);
-// Elements per workgroup currently selected for (prec, N), and the
-// resulting number of AX workgroups for E elements.
+// Elements per workgroup currently selected for (prec, N): ax_tile for the
+// plain operator, pcg_tile for the fused first stage of the solvers; and
+// the resulting number of fused-stage workgroups (partials) for E elements.
 int ax_tile(int prec, int N);
+int pcg_tile(int prec, int N);
 int ax_blocks(int prec, int N, int64_t E);
 
 // Jacobi diagonal of each element (unassembled).

@@ -269,7 +269,7 @@ struct nbx_lp {
     double *zl = nullptr, *part4 = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *g_x = nullptr;
-    int g_iters = 0;
+    int g_iters = 0, g_tile = 0;
 };
 
 namespace nbx {
@@ -443,7 +443,9 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
     NBX_HIP(hipEventRecord(P->ev, cs));
     NBX_HIP(hipStreamWaitEvent(s, P->ev, 0));
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph && (L->gexec == nullptr || L->g_x != x || L->g_iters != chunk)) {
+    const int tile = pcg_tile(NBX_F64, L->P->N);
+    if (o.use_graph &&
+        (L->gexec == nullptr || L->g_x != x || L->g_iters != chunk || L->g_tile != tile)) {
         if (L->gexec) { hipGraphExecDestroy(L->gexec); L->gexec = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -455,7 +457,7 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
         e = hipGraphInstantiate(&L->gexec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e != hipSuccess) { L->gexec = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
-        L->g_x = x; L->g_iters = chunk;
+        L->g_x = x; L->g_iters = chunk; L->g_tile = tile;
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();

@@ -139,8 +139,8 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
                        P->scal32, o.inner_rtol, 0, max_iter);
     NBX_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph &&
-        (P->gexec32 == nullptr || P->g32_iters != chunk || P->g32_fmt != P->inner_fmt)) {
+    if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(NBX_F32, P->N))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -154,6 +154,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
+        P->g32_tile = pcg_tile(NBX_F32, P->N);
     }
     int done = 0;
     while (true) {
@@ -287,8 +288,8 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
     const int nb = sk::red_blocks(P->n);
     const double delta = (o.inner_rtol > 0 && o.inner_rtol < 1) ? o.inner_rtol : 0.1;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph &&
-        (P->gexec32 == nullptr || P->g32_iters != chunk || P->g32_fmt != P->inner_fmt)) {
+    if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(NBX_F32, P->N))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -302,6 +303,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
+        P->g32_tile = pcg_tile(NBX_F32, P->N);
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();

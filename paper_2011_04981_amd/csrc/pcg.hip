@@ -80,7 +80,9 @@ int pcg_f64(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
                        o.rtol, o.fixed_iters, o.max_iter);
     NBX_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 10;
-    if (o.use_graph && (P->gexec == nullptr || P->g_x != x || P->g_iters != chunk)) {
+    const int tile = pcg_tile(NBX_F64, P->N);   // the captured launches bake it in
+    if (o.use_graph &&
+        (P->gexec == nullptr || P->g_x != x || P->g_iters != chunk || P->g_tile != tile)) {
         if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -92,7 +94,7 @@ int pcg_f64(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
         e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e != hipSuccess) { P->gexec = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
-        P->g_x = x; P->g_iters = chunk;
+        P->g_x = x; P->g_iters = chunk; P->g_tile = tile;
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();

@@ -15,15 +15,15 @@ struct nbx_problem {
     double *h_scal = nullptr;   // pinned host mirror of a scalar block
     hipStream_t ws = nullptr;   // the problem's own stream (default priority)
     hipEvent_t ev = nullptr;
-    hipGraphExec_t gexec = nullptr;   // FP64 iterations, captured per (x, chunk)
+    hipGraphExec_t gexec = nullptr;   // FP64 iterations, captured per (x, chunk, tile)
     const double *g_x = nullptr;
-    int g_iters = 0;
+    int g_iters = 0, g_tile = 0;
     // FP32 inner-solve workspace (allocated by the first mixed solve)
     float *G32 = nullptr, *dinv32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr,
           *w32 = nullptr, *d32 = nullptr;
     double *scal32 = nullptr;
     hipGraphExec_t gexec32 = nullptr;
-    int g32_iters = 0, g32_fmt = -1;   // chunk and inner format the graph was captured with
+    int g32_iters = 0, g32_fmt = -1, g32_tile = 0;   // chunk, format, tile of the capture
     // 16-bit factors for the reduced-storage inner operator (NBX_F16 / NBX_BF16)
     uint16_t *G16 = nullptr;
     float *gscale = nullptr;

@@ -36,5 +36,26 @@ def test_tile_table_rejects_invalid_entries():
     assert nbx.get_tile(nbx.F64, 10) in (1, 2, 4)
 
 
+def test_fused_stage_table_is_separate(tmp_path):
+    old = {(p, N): (nbx.get_tile(p, N), nbx.get_pcg_tile(p, N))
+           for p in (nbx.F64, nbx.F32) for N in (8, 10)}
+    try:
+        table = {"f64": {"10": {"epb": 1, "us": {}}},
+                 "pcg_f64": {"10": {"epb": 2, "us": {}}},
+                 "pcg_f32": {"8": {"epb": 4, "us": {}}}}
+        path = autotune.save(table, str(tmp_path / "tiles.json"))
+        assert autotune.load(path) == table
+        assert nbx.get_tile(nbx.F64, 10) == 1 and nbx.get_pcg_tile(nbx.F64, 10) == 2
+        assert nbx.get_pcg_tile(nbx.F32, 8) == 4
+        nbx.set_pcg_tile(nbx.F64, 10, 4)
+        assert nbx.get_tile(nbx.F64, 10) == 1          # the plain table is untouched
+        with pytest.raises(nbx.NbxError):
+            nbx.set_pcg_tile(nbx.F16, 10, 2)
+    finally:
+        for (p, N), (a, b) in old.items():
+            nbx.set_tile(p, N, a)
+            nbx.set_pcg_tile(p, N, b)
+
+
 def test_missing_cache_is_ignored(tmp_path):
     assert autotune.load(str(tmp_path / "absent.json")) is None

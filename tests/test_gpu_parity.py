@@ -370,3 +370,27 @@ def test_mixed_precision_falls_back_when_refinement_stalls():
     x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32, inner_rtol=0.99,
                             mixed_mode=0)
     assert res.fell_back == 1 and res.status == 0 and res.relres <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_stage_tile_change_reaches_captured_solves(prec):
+    """The solvers replay captured graphs; after nbx_pcg_set_tile a solve on
+    the same problem must run the new tile, i.e. agree bit for bit with a
+    solve on a fresh problem (the tile decides how <p,w> partials group)."""
+    b = S.scaled_c2_brick(4, 8)
+    p = nbx.F64 if prec == "f64" else nbx.F32
+    old = nbx.get_pcg_tile(p, b.N)
+    kw = dict(rtol=1e-10, max_iter=3000, check_every=10, prec=p)
+    try:
+        st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+        results = {}
+        for epb in (1, 4):
+            nbx.set_pcg_tile(p, b.N, epb)
+            x, r = st.problem.pcg(st.b, **kw)
+            fresh = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+            xf, rf = fresh.problem.pcg(fresh.b, **kw)
+            assert r.iters == rf.iters and np.array_equal(host(x), host(xf)), epb
+            results[epb] = host(x)
+        assert rel(results[1], results[4]) <= 1e-8      # both are solutions
+    finally:
+        nbx.set_pcg_tile(p, b.N, old)
