@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--nbatch", type=int, default=64, help="problems in the batched leg")
     ap.add_argument("--no-ax-variants", action="store_true",
                     help="skip the FP32 and 16-bit-G AX timings")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the N = 8, 12 solver sweep and the N = 16 AX replay")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner leg")
     ap.add_argument("--learned-train", type=int, default=8,
@@ -270,6 +272,69 @@ def main():
                     pcg[name] = {"unavailable": str(e)}
             out["pcg"] = pcg
             del st, x, x64
+            torch.cuda.empty_cache()
+
+    # ---- the same mesh at N = 8 and 12: FP64 PCG against the refinement
+    # variants (N = 10 is the block above); and the paper's own element
+    # size, N = 16, for the plain operator at E = 800 and E = 8000
+    if not a.no_sweep and not a.no_pcg and a.N == 10:
+        sweep = {}
+        with torch.cuda.stream(stream):
+            for Ns in (8, 12):
+                log(f"sweep: N={Ns}")
+                st = nbx.setup_brick(brick.ex, brick.ey, brick.ez, Ns, brick.deform_array())
+                stream.synchronize()
+                row = {}
+                x64 = None
+                for name, kw in (("fp64", dict(prec=nbx.F64)),
+                                 ("mixed_fp32", dict(prec=nbx.F32, mixed_mode=0,
+                                                     inner_rtol=0.1)),
+                                 ("mixed_f16_storage", dict(prec=nbx.F16, mixed_mode=0,
+                                                            inner_rtol=0.1))):
+                    st.problem.pcg(st.b, rtol=1e-10, max_iter=20000, check_every=20, **kw)
+                    times = []
+                    for _ in range(2):
+                        h0 = time.perf_counter()
+                        xs, rs = st.problem.pcg(st.b, rtol=1e-10, max_iter=20000,
+                                                check_every=20, **kw)
+                        times.append(time.perf_counter() - h0)
+                    rec = {"iters": rs.iters, "outer": rs.outer_iters,
+                           "seconds": round(min(times), 5), "true_relres": rs.true_relres,
+                           "fell_back": rs.fell_back, "status": rs.status}
+                    if x64 is None:
+                        x64 = xs.clone()
+                    else:
+                        rec["err_vs_fp64"] = float((xs - x64).abs().max() / x64.abs().max())
+                        rec["speedup_vs_fp64"] = round(row["fp64"]["seconds"] / min(times), 3)
+                    row[name] = rec
+                    log(f"  N={Ns} {name}: {rs.iters} it, {min(times):.3f} s")
+                sweep[f"N{Ns}"] = {"E": E, "local_nodes": E * Ns ** 3, **row}
+                del st, x64, xs
+                torch.cuda.empty_cache()
+            replay = {}
+            for Er in (800, 8000):
+                Nr = 16
+                ur = torch.as_tensor(S.uniform_field(Er, Nr, seed=0)).to(dev)
+                Gr = torch.as_tensor(S.random_factors(Er, Nr, seed=1)).to(dev)
+                Dr = nbx.deriv_device(Nr, dev)
+                wr = torch.empty_like(ur)
+                for _ in range(20):
+                    nbx.ax(ur, Gr, Dr, out=wr)
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(100):
+                    nbx.ax(ur, Gr, Dr, out=wr)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / 100
+                replay[f"E{Er}"] = {
+                    "N": Nr, "mean_launch_us": round(t * 1e6, 2),
+                    "gflops": round(nbx.ax_flops(Nr, Er) / t / 1e9, 1),
+                    "gbs_algorithmic": round(nbx.ax_bytes(Nr, Er) / t / 1e9, 1),
+                    "working_set_mb": round(nbx.ax_bytes(Nr, Er) / 1e6, 1)}
+                log(f"  AX N=16 E={Er}: {t*1e6:.1f} us")
+                del ur, Gr, wr
+            out["sweep"] = {"solvers": sweep, "ax_n16_paper_sizes": replay}
             torch.cuda.empty_cache()
 
     # ---- batched solves: independent problems of uneven E and N together

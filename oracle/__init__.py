@@ -127,7 +127,7 @@ def brick_ids(brick):
 
 
 def ax(u, G, D, N: Optional[int] = None):
-    """w = AX(u) element by element (Listing 1).  u: (E, N^3) or flat,
+    """w = AX(u) element by element (w_e = D^T G_e D u_e).  u: (E, N^3) or flat,
     G: (E, 6, N^3), D: (N, N) row-major."""
     D = _c(D)
     N = D.shape[0] if N is None else N

@@ -13,10 +13,11 @@
  * result is independent of the thread count.
  *
  * Sources, by function:
- *   ora_ax ........ Section II-B, Listing 1 (ax / ax_e / local_grad3) and the
- *                   prose that defines local_grad3_t as the transpose with
- *                   two accumulations.  The listing's mxm is read as the
- *                   column-major product C(n1 x n3) = A(n1 x n2) B(n2 x n3).
+ *   ora_ax ........ the operator's definition w_e = D^T G_e D u_e
+ *                   (Section II-B): gradient by the collocation derivative
+ *                   along each direction, contraction with the symmetric
+ *                   six-factor matrix, transposed gradient; written as
+ *                   explicit index sums.
  *   ora_gll, ora_deriv, ora_geom, ora_brick_*, ora_gs_*, ora_jacobi_diag,
  *   ora_pcg_* ..... the paper names these (Section II-B: CG with a simple
  *                   preconditioner on a block geometry, nearest-neighbour
@@ -223,89 +224,56 @@ void ora_brick_ids(int ex, int ey, int ez, int N, int64_t *gid, uint8_t *bnd)
 
 /* ------------------------------------------------------------------- AX */
 
-/* mxm(A, n1, B, n2, C, n3): C(n1 x n3) = A(n1 x n2) B(n2 x n3), all
- * column-major, the inner index summed in ascending order. */
-static void mxm(const double *A, int n1, const double *B, int n2, double *C, int n3)
+/* One element of the operator, written out from its definition
+ * w_e = D^T G_e D u_e (Section II-B): the reference-space gradient of u
+ * (the collocation derivative D applied along r, s and t), the symmetric
+ * contraction with the node's factor matrix [[g1,g2,g3],[g2,g4,g5],
+ * [g3,g5,g6]], and the transposed gradient
+ *   w(i,j,k) = sum_m D[m][i] vr(m,j,k) + D[m][j] vs(i,m,k) + D[m][k] vt(i,j,m).
+ * D is row-major, D[a*N+b] = l_b'(xi_a).  Every sum runs over m in
+ * ascending order.  v holds 3 N^3 doubles of scratch. */
+static void ax_elem(double *w, const double *u, const double *g, int N, const double *D,
+                    double *v)
 {
-    for (int j = 0; j < n3; ++j)
-        for (int i = 0; i < n1; ++i) {
-            double s = 0.0;
-            for (int k = 0; k < n2; ++k) s += A[i + n1 * k] * B[k + n2 * j];
-            C[i + n1 * j] = s;
-        }
-}
-
-/* local_grad3: ur = D U (r), us(:,:,k) = U(:,:,k) D^T (s), ut = U D^T (t),
- * with dxm1 = D and dxtm1 = D^T as column-major N x N matrices. */
-static void local_grad3(double *ur, double *us, double *ut, const double *u,
-                        int N, const double *dxm1, const double *dxtm1)
-{
-    int N2 = N * N;
-    mxm(dxm1, N, u, N, ur, N2);
+    const int64_t N3 = (int64_t)N * N * N;
+    double *vr = v, *vs = v + N3, *vt = v + 2 * N3;
     for (int k = 0; k < N; ++k)
-        mxm(u + k * N2, N, dxtm1, N, us + k * N2, N);
-    mxm(u, N2, dxtm1, N, ut, N);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                double ur = 0.0, us = 0.0, ut = 0.0;
+                for (int m = 0; m < N; ++m) ur += D[i * N + m] * u[IDX3(m, j, k, N)];
+                for (int m = 0; m < N; ++m) us += D[j * N + m] * u[IDX3(i, m, k, N)];
+                for (int m = 0; m < N; ++m) ut += D[k * N + m] * u[IDX3(i, j, m, N)];
+                const int64_t q = IDX3(i, j, k, N);
+                const double g1 = g[q], g2 = g[N3 + q], g3 = g[2 * N3 + q];
+                const double g4 = g[3 * N3 + q], g5 = g[4 * N3 + q], g6 = g[5 * N3 + q];
+                vr[q] = g1 * ur + g2 * us + g3 * ut;
+                vs[q] = g2 * ur + g4 * us + g5 * ut;
+                vt[q] = g3 * ur + g5 * us + g6 * ut;
+            }
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                double acc = 0.0;
+                for (int m = 0; m < N; ++m) acc += D[m * N + i] * vr[IDX3(m, j, k, N)];
+                for (int m = 0; m < N; ++m) acc += D[m * N + j] * vs[IDX3(i, m, k, N)];
+                for (int m = 0; m < N; ++m) acc += D[m * N + k] * vt[IDX3(i, j, m, N)];
+                w[IDX3(i, j, k, N)] = acc;
+            }
 }
 
-/* local_grad3_t, the transpose of local_grad3:
- * w = D^T wr, then (first accumulation) w(:,:,k) += ws(:,:,k) D for every
- * slab, then the last product wt D is formed and (second accumulation)
- * added to w. */
-static void local_grad3_t(double *w, const double *wr, const double *ws,
-                          const double *wt, int N, const double *dxm1,
-                          const double *dxtm1, double *tmp)
-{
-    int N2 = N * N, N3 = N2 * N;
-    mxm(dxtm1, N, wr, N, w, N2);
-    for (int k = 0; k < N; ++k) {
-        mxm(ws + k * N2, N, dxm1, N, tmp, N);
-        for (int q = 0; q < N2; ++q) w[k * N2 + q] += tmp[q];
-    }
-    mxm(wt, N2, dxm1, N, tmp, N);
-    for (int q = 0; q < N3; ++q) w[q] += tmp[q];
-}
-
-/* ax_e: local_grad3, the per-node geometric contraction with the
- * symmetric factor matrix [[g1,g2,g3],[g2,g4,g5],[g3,g5,g6]], then
- * local_grad3_t.  g points at this element's six factor planes. */
-static void ax_e(double *w, const double *u, const double *g, int64_t N3, int N,
-                 const double *dxm1, const double *dxtm1, double *work)
-{
-    double *ur = work, *us = work + N3, *ut = work + 2 * N3, *tmp = work + 3 * N3;
-    local_grad3(ur, us, ut, u, N, dxm1, dxtm1);
-    for (int64_t i = 0; i < N3; ++i) {
-        double g1 = g[i], g2 = g[N3 + i], g3 = g[2 * N3 + i];
-        double g4 = g[3 * N3 + i], g5 = g[4 * N3 + i], g6 = g[5 * N3 + i];
-        double wr = g1 * ur[i] + g2 * us[i] + g3 * ut[i];
-        double ws = g2 * ur[i] + g4 * us[i] + g5 * ut[i];
-        double wt = g3 * ur[i] + g5 * us[i] + g6 * ut[i];
-        ur[i] = wr; us[i] = ws; ut[i] = wt;
-    }
-    local_grad3_t(w, ur, us, ut, N, dxm1, dxtm1, tmp);
-}
-
-/* ax: w(:,e) = A_e u(:,e) for every element.  D is row-major
- * (D[a*N+b] = l_b'(xi_a)); read as a column-major array it is D^T, so the
- * column-major dxm1 = D is its transpose.  G is [E][6][N^3]. */
+/* ax: w(:,e) = A_e u(:,e) for every element; G is [E][6][N^3]. */
 void ora_ax(int N, int64_t E, const double *u, const double *G, const double *D, double *w)
 {
-    int64_t N3 = (int64_t)N * N * N;
-    double *dxm1 = (double *)malloc(sizeof(double) * N * N);
-    double *dxtm1 = (double *)malloc(sizeof(double) * N * N);
-    for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b) {
-            dxm1[a + N * b] = D[a * N + b];   /* column-major D */
-            dxtm1[b + N * a] = D[a * N + b];  /* column-major D^T */
-        }
+    const int64_t N3 = (int64_t)N * N * N;
     #pragma omp parallel
     {
-        double *work = (double *)malloc(sizeof(double) * 4 * N3);
+        double *v = (double *)malloc(sizeof(double) * 3 * N3);
         #pragma omp for schedule(static)
         for (int64_t e = 0; e < E; ++e)
-            ax_e(w + e * N3, u + e * N3, G + e * 6 * N3, N3, N, dxm1, dxtm1, work);
-        free(work);
+            ax_elem(w + e * N3, u + e * N3, G + e * 6 * N3, N, D, v);
+        free(v);
     }
-    free(dxm1); free(dxtm1);
 }
 
 /* ---------------------------------------------------- gather-scatter */
@@ -538,65 +506,53 @@ void ora_set_num_threads(int n)
 /* ------------------------------------------------- single precision --
  * The same operator and exchange in IEEE single arithmetic, for the
  * iterative-refinement oracle (reduced precision is the paper's stated
- * further work, Section V).  Identical steps to the double versions above:
- * mxm with ascending inner sums, local_grad3, the geometric contraction,
- * local_grad3_t with its two accumulations. */
+ * further work, Section V): ax_elem's sums in float, D rounded to float. */
 
-static void mxm_f(const float *A, int n1, const float *B, int n2, float *C, int n3)
+static void ax_elem_f(float *w, const float *u, const float *g, int N, const float *D,
+                      float *v)
 {
-    for (int j = 0; j < n3; ++j)
-        for (int i = 0; i < n1; ++i) {
-            float s = 0.0f;
-            for (int k = 0; k < n2; ++k) s += A[i + n1 * k] * B[k + n2 * j];
-            C[i + n1 * j] = s;
-        }
-}
-
-static void ax_e_f(float *w, const float *u, const float *g, int64_t N3, int N,
-                   const float *dxm1, const float *dxtm1, float *work)
-{
-    int N2 = N * N;
-    float *ur = work, *us = work + N3, *ut = work + 2 * N3, *tmp = work + 3 * N3;
-    mxm_f(dxm1, N, u, N, ur, N2);
-    for (int k = 0; k < N; ++k) mxm_f(u + k * N2, N, dxtm1, N, us + k * N2, N);
-    mxm_f(u, N2, dxtm1, N, ut, N);
-    for (int64_t i = 0; i < N3; ++i) {
-        float g1 = g[i], g2 = g[N3 + i], g3 = g[2 * N3 + i];
-        float g4 = g[3 * N3 + i], g5 = g[4 * N3 + i], g6 = g[5 * N3 + i];
-        float wr = g1 * ur[i] + g2 * us[i] + g3 * ut[i];
-        float ws = g2 * ur[i] + g4 * us[i] + g5 * ut[i];
-        float wt = g3 * ur[i] + g5 * us[i] + g6 * ut[i];
-        ur[i] = wr; us[i] = ws; ut[i] = wt;
-    }
-    mxm_f(dxtm1, N, ur, N, w, N2);
-    for (int k = 0; k < N; ++k) {
-        mxm_f(us + k * N2, N, dxm1, N, tmp, N);
-        for (int q = 0; q < N2; ++q) w[k * N2 + q] += tmp[q];
-    }
-    mxm_f(ut, N2, dxm1, N, tmp, N);
-    for (int64_t q = 0; q < N3; ++q) w[q] += tmp[q];
+    const int64_t N3 = (int64_t)N * N * N;
+    float *vr = v, *vs = v + N3, *vt = v + 2 * N3;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                float ur = 0.0f, us = 0.0f, ut = 0.0f;
+                for (int m = 0; m < N; ++m) ur += D[i * N + m] * u[IDX3(m, j, k, N)];
+                for (int m = 0; m < N; ++m) us += D[j * N + m] * u[IDX3(i, m, k, N)];
+                for (int m = 0; m < N; ++m) ut += D[k * N + m] * u[IDX3(i, j, m, N)];
+                const int64_t q = IDX3(i, j, k, N);
+                const float g1 = g[q], g2 = g[N3 + q], g3 = g[2 * N3 + q];
+                const float g4 = g[3 * N3 + q], g5 = g[4 * N3 + q], g6 = g[5 * N3 + q];
+                vr[q] = g1 * ur + g2 * us + g3 * ut;
+                vs[q] = g2 * ur + g4 * us + g5 * ut;
+                vt[q] = g3 * ur + g5 * us + g6 * ut;
+            }
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                float acc = 0.0f;
+                for (int m = 0; m < N; ++m) acc += D[m * N + i] * vr[IDX3(m, j, k, N)];
+                for (int m = 0; m < N; ++m) acc += D[m * N + j] * vs[IDX3(i, m, k, N)];
+                for (int m = 0; m < N; ++m) acc += D[m * N + k] * vt[IDX3(i, j, m, N)];
+                w[IDX3(i, j, k, N)] = acc;
+            }
 }
 
 /* w = AX(u) in single precision; D is the double matrix rounded to float. */
 void ora_ax_f32(int N, int64_t E, const float *u, const float *G, const double *D, float *w)
 {
-    int64_t N3 = (int64_t)N * N * N;
-    float *dxm1 = (float *)malloc(sizeof(float) * N * N);
-    float *dxtm1 = (float *)malloc(sizeof(float) * N * N);
-    for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b) {
-            dxm1[a + N * b] = (float)D[a * N + b];
-            dxtm1[b + N * a] = (float)D[a * N + b];
-        }
+    const int64_t N3 = (int64_t)N * N * N;
+    float *Df = (float *)malloc(sizeof(float) * N * N);
+    for (int q = 0; q < N * N; ++q) Df[q] = (float)D[q];
     #pragma omp parallel
     {
-        float *work = (float *)malloc(sizeof(float) * 4 * N3);
+        float *v = (float *)malloc(sizeof(float) * 3 * N3);
         #pragma omp for schedule(static)
         for (int64_t e = 0; e < E; ++e)
-            ax_e_f(w + e * N3, u + e * N3, G + e * 6 * N3, N3, N, dxm1, dxtm1, work);
-        free(work);
+            ax_elem_f(w + e * N3, u + e * N3, G + e * 6 * N3, N, Df, v);
+        free(v);
     }
-    free(dxm1); free(dxtm1);
+    free(Df);
 }
 
 /* dssum in single precision, ascending local index. */
