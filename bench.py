@@ -156,14 +156,15 @@ def main():
         variants = {}
         u32 = u.float()
         w32 = torch.empty_like(u32)
-        G32 = G.float()
-        runs = {"fp32": (lambda: nbx.ax(u32, G32, D, out=w32), 32)}
-        G16f, gsf = nbx.g16_pack(G, N, nbx.F16)
-        G16b, gsb = nbx.g16_pack(G, N, nbx.BF16)
-        runs["g_fp16"] = (lambda: nbx.ax_g16(u32, G16f, gsf, D, nbx.F16, out=w32), 20)
-        runs["g_bf16"] = (lambda: nbx.ax_g16(u32, G16b, gsb, D, nbx.BF16, out=w32), 20)
-        if a.no_ax_variants:
-            runs = {}
+        G32 = G.float() if not a.no_ax_variants else None
+        runs = {}
+        G16f = gsf = G16b = gsb = None
+        if not a.no_ax_variants:
+            runs["fp32"] = (lambda: nbx.ax(u32, G32, D, out=w32), 32)
+            G16f, gsf = nbx.g16_pack(G, N, nbx.F16)
+            G16b, gsb = nbx.g16_pack(G, N, nbx.BF16)
+            runs["g_fp16"] = (lambda: nbx.ax_g16(u32, G16f, gsf, D, nbx.F16, out=w32), 20)
+            runs["g_bf16"] = (lambda: nbx.ax_g16(u32, G16b, gsb, D, nbx.BF16, out=w32), 20)
         for name, (fn, bpn) in runs.items():
             for _ in range(50):
                 fn()
