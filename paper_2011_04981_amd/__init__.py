@@ -153,6 +153,14 @@ def _dptr(t, dtype=None, name="tensor"):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(t, n: int, name: str):
+    """The library reads or writes exactly n elements through this tensor:
+    refuse anything else before a kernel can run past its end."""
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
 def _stream(stream=None):
     torch = _torch()
     s = torch.cuda.current_stream() if stream is None else stream
@@ -211,6 +219,8 @@ def geom_brick(ex: int, ey: int, ez: int, N: int, deform=None, with_xyz=False,
 
 def geom(xyz, N: int, stream=None):
     torch = _torch()
+    if xyz.dim() != 3 or xyz.shape[0] != 3 or xyz.shape[2] != N ** 3:
+        raise ValueError("xyz must be [3, E, N^3]")
     E = xyz.shape[1]
     G = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=xyz.device)
     bm = torch.empty((E, N ** 3), dtype=torch.float64, device=xyz.device)
@@ -235,6 +245,8 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[in
     torch = _torch()
     N = D.shape[0] if N is None else N
     E = u.numel() // N ** 3
+    _need(u, E * N ** 3, "u")
+    _need(D, N * N, "D")
     prec = {torch.float64: F64, torch.float32: F32}.get(u.dtype)
     if prec is None:
         raise TypeError(f"unsupported dtype {u.dtype}")
@@ -242,7 +254,7 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[in
         raise TypeError("G and u must share a dtype")
     if G.numel() != 6 * u.numel():
         raise ValueError("G must hold 6 factors per node")
-    w = torch.empty_like(u) if out is None else out
+    w = torch.empty_like(u) if out is None else _need(out, u.numel(), "out")
     if epb is None:
         _check(lib().nbx_ax(prec, _dptr(u, name="u"), _dptr(G, name="G"),
                             _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
@@ -260,6 +272,7 @@ def g16_pack(G, N: int, gprec: int, stream=None):
     scales (nbx_g16_pack)."""
     torch = _torch()
     E = G.numel() // (6 * N ** 3)
+    _need(G, 6 * E * N ** 3, "G")
     G16 = torch.empty((E, 6, N ** 3), dtype=torch.int16, device=G.device)
     gs = torch.empty(E, dtype=torch.float32, device=G.device)
     _check(lib().nbx_g16_pack(gprec, _dptr(G, torch.float64, "G"), N, E, _dptr(G16),
@@ -274,6 +287,7 @@ def ax_g16(u, G16, gscale, D, gprec: int, out=None, stream=None):
     E = u.numel() // N ** 3
     if u.numel() != E * N ** 3 or G16.numel() != 6 * u.numel() or gscale.numel() != E:
         raise ValueError("u [E, N^3], G16 [E, 6, N^3] and gscale [E] must agree")
+    _need(D, N * N, "D")
     w = torch.empty_like(u) if out is None else out
     if w.numel() != u.numel():
         raise ValueError("out must match u")
@@ -309,6 +323,8 @@ class GS:
         gid = np.ascontiguousarray(gid, dtype=np.int64).reshape(-1)
         self.n = gid.size
         b = None if bnd is None else np.ascontiguousarray(bnd, dtype=np.uint8).reshape(-1)
+        if b is not None and b.size != self.n:
+            raise ValueError("one Dirichlet flag per local node")
         h = C.c_void_p()
         _check(lib().nbx_gs_create(_hptr(gid), _hptr(b) if b is not None else None,
                                    self.n, C.byref(h)), "nbx_gs_create")
@@ -332,6 +348,7 @@ class GS:
     def dssum(self, v, mask: bool = True, stream=None):
         torch = _torch()
         prec = {torch.float64: F64, torch.float32: F32}[v.dtype]
+        _need(v, self.n, "v")
         _check(lib().nbx_dssum(self._h, prec, _dptr(v), 1 if mask else 0, _stream(stream)),
                "nbx_dssum")
         return v
@@ -347,6 +364,10 @@ class GS:
 def jacobi_setup(G, D, gs: GS, N: int, stream=None):
     torch = _torch()
     E = G.shape[0]
+    _need(G, 6 * E * N ** 3, "G")
+    _need(D, N * N, "D")
+    if gs.n != E * N ** 3:
+        raise ValueError("the gather-scatter plan does not match G")
     dinv = torch.empty((E, N ** 3), dtype=torch.float64, device=G.device)
     _check(lib().nbx_jacobi_setup(_dptr(G, torch.float64), _dptr(D, torch.float64), N, E,
                                   gs.handle, _dptr(dinv), _stream(stream)), "nbx_jacobi_setup")
@@ -365,6 +386,8 @@ def sine_source(xyz, stream=None):
 
 def rhs(gs: GS, bm, f, stream=None):
     torch = _torch()
+    _need(bm, gs.n, "bm")
+    _need(f, gs.n, "f")
     b = torch.empty_like(bm)
     _check(lib().nbx_rhs(gs.handle, _dptr(bm, torch.float64), _dptr(f, torch.float64),
                          bm.numel(), _dptr(b), _stream(stream)), "nbx_rhs")
@@ -402,6 +425,11 @@ class Problem:
         torch = _torch()
         self.G, self.D, self.N, self.gs = G, D, N, gs
         self.E = G.shape[0]
+        self.n = self.E * N ** 3
+        _need(G, 6 * self.n, "G")
+        _need(D, N * N, "D")
+        if gs.n != self.n:
+            raise ValueError("the gather-scatter plan does not match G")
         h = C.c_void_p()
         _check(lib().nbx_problem_create(_dptr(G, torch.float64), _dptr(D, torch.float64), N,
                                         self.E, gs.handle, C.byref(h), _stream(stream)),
@@ -427,7 +455,8 @@ class Problem:
 
     def pcg(self, b, x=None, stream=None, **opts) -> tuple:
         torch = _torch()
-        x = torch.empty_like(b) if x is None else x
+        _need(b, self.n, "b")
+        x = torch.empty_like(b) if x is None else _need(x, self.n, "x")
         o = default_opts(**opts)
         r = PcgResult()
         st = lib().nbx_pcg(self._h, _dptr(b, torch.float64, "b"), _dptr(x, torch.float64, "x"),
@@ -439,6 +468,9 @@ class Problem:
 
     def pcg_iterate(self, x, r, z, p, scal, n_iter: int, stream=None):
         torch = _torch()
+        for t, nm in ((x, "x"), (r, "r"), (z, "z"), (p, "p")):
+            _need(t, self.n, nm)
+        _need(scal, SCAL_LEN, "scal")
         _check(lib().nbx_pcg_iterate(self._h, _dptr(x, torch.float64), _dptr(r, torch.float64),
                                      _dptr(z, torch.float64), _dptr(p, torch.float64),
                                      _dptr(scal, torch.float64), n_iter, _stream(stream)),
@@ -495,7 +527,13 @@ def pcg_batched(problems, bs, xs=None, stream=None, **opts):
     n = len(problems)
     if len(bs) != n:
         raise ValueError("one right-hand side per problem")
+    for P, b in zip(problems, bs):
+        _need(b, P.n, "b")
     xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+    if len(xs) != n:
+        raise ValueError("one solution vector per problem")
+    for P, x in zip(problems, xs):
+        _need(x, P.n, "x")
     P_arr = (C.c_void_p * n)(*[p._h.value for p in problems])
     b_arr = (C.c_void_p * n)(*[_dptr(b, torch.float64, "b").value for b in bs])
     x_arr = (C.c_void_p * n)(*[_dptr(x, torch.float64, "x").value for x in xs])
@@ -517,6 +555,8 @@ def gemm_bf16(A, B, trans_a=False, trans_b=False, stream=None):
     torch = _torch()
     if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
         raise TypeError("operands must be bfloat16")
+    if A.dim() != 2 or B.dim() != 2:
+        raise ValueError("operands must be matrices")
     M, K = (A.shape[1], A.shape[0]) if trans_a else (A.shape[0], A.shape[1])
     Kb, N = (B.shape[1], B.shape[0]) if trans_b else (B.shape[0], B.shape[1])
     if K != Kb:
@@ -558,6 +598,7 @@ class Mlp:
 
     def set_params(self, params, stream=None):
         torch = _torch()
+        _need(params, self.n_params, "params")
         _check(lib().nbx_mlp_set_params(self._h, _dptr(params, torch.float32), _stream(stream)),
                "nbx_mlp_set_params")
 
@@ -572,8 +613,15 @@ class Mlp:
                    "nbx_mlp_get_params")
         return out
 
+    def _rows(self, X, T=None):
+        if X.dim() != 2 or X.shape[1] != self.in_pad:
+            raise ValueError(f"X must be [B, {self.in_pad}]")
+        if T is not None and (T.dim() != 2 or tuple(T.shape) != (X.shape[0], self.out_pad)):
+            raise ValueError(f"T must be [B, {self.out_pad}]")
+
     def forward(self, X, stream=None):
         torch = _torch()
+        self._rows(X)
         Y = torch.empty((X.shape[0], self.out_pad), dtype=torch.float32, device=X.device)
         _check(lib().nbx_mlp_forward(self._h, _dptr(X, torch.bfloat16), X.shape[0], _dptr(Y),
                                      _stream(stream)), "nbx_mlp_forward")
@@ -581,6 +629,7 @@ class Mlp:
 
     def grad(self, X, T, stream=None):
         torch = _torch()
+        self._rows(X, T)
         loss = torch.empty(1, dtype=torch.float64, device=X.device)
         _check(lib().nbx_mlp_grad(self._h, _dptr(X, torch.bfloat16), _dptr(T, torch.float32),
                                   X.shape[0], _dptr(loss), _stream(stream)), "nbx_mlp_grad")
@@ -588,6 +637,7 @@ class Mlp:
 
     def train_step(self, X, T, lr: float, stream=None):
         torch = _torch()
+        self._rows(X, T)
         loss = torch.empty(1, dtype=torch.float64, device=X.device)
         _check(lib().nbx_mlp_train_step(self._h, _dptr(X, torch.bfloat16),
                                         _dptr(T, torch.float32), X.shape[0], float(lr),
@@ -638,6 +688,7 @@ class LearnedPrecond:
 
     def apply(self, r, stream=None):
         torch = _torch()
+        _need(r, self.problem.n, "r")
         z = torch.empty_like(r)
         _check(lib().nbx_lp_apply(self._h, _dptr(r, torch.float64), _dptr(z), _stream(stream)),
                "nbx_lp_apply")
@@ -646,6 +697,8 @@ class LearnedPrecond:
     def samples(self, r, xstar, x, elems, stream=None):
         """(X [n, in_pad] bf16, T [n, out_pad] f32) for the element indices."""
         torch = _torch()
+        for t, nm in ((r, "r"), (xstar, "xstar"), (x, "x")):
+            _need(t, self.problem.n, nm)
         n = elems.numel()
         X = torch.empty((n, self.net.in_pad), dtype=torch.bfloat16, device="cuda")
         T = torch.empty((n, self.net.out_pad), dtype=torch.float32, device="cuda")
@@ -666,7 +719,8 @@ class LearnedPrecond:
 
     def pcg(self, b, x=None, stream=None, **opts):
         torch = _torch()
-        x = torch.empty_like(b) if x is None else x
+        _need(b, self.problem.n, "b")
+        x = torch.empty_like(b) if x is None else _need(x, self.problem.n, "x")
         o = default_opts(**opts)
         r = PcgResult()
         st = lib().nbx_pcg_learned(self._h, _dptr(b, torch.float64), _dptr(x, torch.float64),

@@ -394,3 +394,27 @@ def test_fused_stage_tile_change_reaches_captured_solves(prec):
         assert rel(results[1], results[4]) <= 1e-8      # both are solutions
     finally:
         nbx.set_pcg_tile(p, b.N, old)
+
+
+def test_binding_refuses_mis_sized_tensors():
+    """The C ABI takes raw pointers; the binding checks sizes before any
+    launch could run past a buffer."""
+    b = S.scaled_c2_brick(2, 4)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    n = st.E * st.N ** 3
+    short = torch.zeros(n - 1, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        st.problem.pcg(short)
+    with pytest.raises(ValueError):
+        st.gs.dssum(short)
+    with pytest.raises(ValueError):
+        nbx.ax(torch.zeros((st.E, st.N ** 3), dtype=torch.float64, device=DEV), st.G, st.D,
+               out=short)
+    with pytest.raises(ValueError):
+        nbx.ax(torch.zeros((st.E, st.N ** 3), dtype=torch.float64, device=DEV), st.G[:1], st.D)
+    net = nbx.Mlp(st.N ** 3 + 6, 64, st.N ** 3, max_batch=64)
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros((64, 8), dtype=torch.bfloat16, device=DEV))
+    # the solve still works afterwards
+    x, r = st.problem.pcg(st.b, rtol=1e-10)
+    assert r.status == 0
