@@ -138,8 +138,8 @@ lp_beta_kernel(int nb, const double *__restrict__ part, double *__restrict__ sca
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     __shared__ double s[2][16];
-    double a = 0, b = 0;
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    double a, b;
+    sk::partial_sums2(nb, part, a, b);
     a = sk::wsum(a); b = sk::wsum(b);
     if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
     __syncthreads();
@@ -182,8 +182,8 @@ lp_rr_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     __shared__ double s[16];
-    double a = 0;
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) a += part[2 * q];
+    double a, unused;
+    sk::partial_sums2(nb, part, a, unused);
     a = sk::wsum(a);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = a;
     __syncthreads();

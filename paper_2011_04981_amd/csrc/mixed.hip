@@ -55,7 +55,7 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
 {
     const GsPlan &gs = P->gs->plan;
     const int nb1 = ax_blocks(NBX_F32, P->N, P->E);
-    const int nb3 = sk::red_blocks(P->n);
+    const int nb3 = sk::red_blocks(P->n, sk::Vec<float>::W);
     for (int it = 0; it < n_iter; ++it) {
         int st = P->inner_fmt == NBX_F32
                      ? ax_pcg_launch_f32(P->G32, P->D, P->N, P->E, P->z32, P->p32, P->w32,
@@ -252,8 +252,8 @@ __global__ void __launch_bounds__(1024)
 reliable_reduce_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
 {
     __shared__ double s[2][16];
-    double a = 0, b = 0;
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) { a += part[2 * q]; b += part[2 * q + 1]; }
+    double a, b;
+    sk::partial_sums2(nb, part, a, b);
     a = sk::wsum(a); b = sk::wsum(b);
     if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
     __syncthreads();
