@@ -418,3 +418,40 @@ def test_binding_refuses_mis_sized_tensors():
     # the solve still works afterwards
     x, r = st.problem.pcg(st.b, rtol=1e-10)
     assert r.status == 0
+
+
+def test_full_size_solves_checked_by_the_oracle_operator():
+    """The benchmark's 32^3 deformed brick at N = 10 (32.8 M local nodes), in
+    the configuration bench.py times: FP64 PCG and the FP32 / FP16-storage
+    refinement solves to 1e-10; the oracle builds its own geometry and
+    right-hand side and evaluates ||b - A x||_c / ||b||_c for each GPU
+    solution with its own operator."""
+    b = S.c2_brick()
+    print("full-size set-up (oracle)", flush=True)
+    P = O.setup(b)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    bb = O.wdot(P.c, P.b, P.b)
+    for name, kw in (("fp64", dict(prec=nbx.F64)),
+                     ("fp32", dict(prec=nbx.F32, inner_rtol=0.1)),
+                     ("f16", dict(prec=nbx.F16, inner_rtol=0.1))):
+        print(f"full-size solve {name}", flush=True)
+        x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=10000, check_every=20, **kw)
+        assert r.status == 0 and r.flag == 1, (name, r)
+        xh = host(x).reshape(-1)
+        res = P.b - P.apply_A(xh)
+        rel_true = np.sqrt(O.wdot(P.c, res, res) / bb)
+        print(f"{name}: {r.iters} it, oracle-operator relres {rel_true:.2e}")
+        assert rel_true <= 2e-10, (name, rel_true)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_pcg_tiny_elements(N):
+    """Degenerate element orders: N = 2 (trilinear, no interior nodes) and
+    N = 3; the solve must match the oracle's."""
+    b = S.Brick(5, 4, 3, N, ((0.05, 2, 2, 2),) * 3)
+    P = O.setup(b)
+    ora = O.pcg(P, max_iter=3000, rtol=1e-10)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=3000, check_every=3)
+    assert r.status == 0 and abs(r.iters - ora.iters) <= 1
+    assert rel(host(x), ora.x) <= 1e-8
