@@ -275,6 +275,33 @@ def main():
             del st, x, x64
             torch.cuda.empty_cache()
 
+    # ---- C1: the 4x4x4 affine brick at N = 10 (4 MB working set, cache
+    # resident): AX and 100 FP64 PCG iterations
+    if not a.no_pcg and a.N == 10:
+        with torch.cuda.stream(stream):
+            c1 = S.c1_brick()
+            st1 = nbx.setup_brick(c1.ex, c1.ey, c1.ez, c1.N)
+            u1 = torch.as_tensor(S.uniform_field(c1.E, c1.N, seed=0)).to(dev)
+            w1 = torch.empty_like(u1)
+            for _ in range(50):
+                nbx.ax(u1, st1.G, st1.D, out=w1)
+            per1 = []
+            for _ in range(100):
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                nbx.ax(u1, st1.G, st1.D, out=w1)
+                e1.record(stream)
+                per1.append((e0, e1))
+            torch.cuda.synchronize()
+            t1 = statistics.median(s_.elapsed_time(e_) * 1e-3 for s_, e_ in per1)
+            st1.problem.pcg(st1.b, max_iter=100, fixed_iters=1, check_every=20)
+            _, r1 = st1.problem.pcg(st1.b, max_iter=100, fixed_iters=1, check_every=20)
+            out["c1"] = {"E": c1.E, "N": 10, "ax_median_us": round(t1 * 1e6, 2),
+                         "ax_gflops": round(nbx.ax_flops(10, c1.E) / t1 / 1e9, 1),
+                         "pcg_100_iterations_seconds": round(r1.seconds, 5)}
+            log(f"C1: AX {t1*1e6:.1f} us, 100 PCG iterations {r1.seconds*1e3:.2f} ms")
+            del st1, u1, w1
+
     # ---- the same mesh at N = 8 and 12: FP64 PCG against the refinement
     # variants (N = 10 is the block above); and the paper's own element
     # size, N = 16, for the plain operator at E = 800 and E = 8000
@@ -414,6 +441,36 @@ def main():
             "sample": f"oracle AX on {sb.E} elements ({a.n}x{a.n}x{ez} slab of the same "
                       f"deformed mapping, N={N}), {reps} applications in {dt:.1f} s"}
         log(f"cpu oracle: {out['cpu_baseline']['value']} GFLOP/s on {O.num_threads()} threads")
+        # the small affine brick C1 (4x4x4, N = 10) on one core and on all, 100
+        # oracle PCG iterations on C1, and the oracle's PCG iteration on the
+        # benchmark brick
+        c1 = S.c1_brick()
+        P1 = O.setup(c1)
+        u1 = S.uniform_field(c1.E, c1.N, seed=0)
+        extra = {}
+        all_threads = O.num_threads()
+        for label, nt in (("1core", 1), ("allcores", all_threads)):
+            O.set_num_threads(nt)
+            O.ax(u1, P1.G, P1.D)
+            reps, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < 1.0:
+                O.ax(u1, P1.G, P1.D)
+                reps += 1
+            dt = time.perf_counter() - t0
+            extra[f"c1_ax_gflops_{label}"] = round(nbx.ax_flops(10, c1.E) * reps / dt / 1e9, 3)
+        O.set_num_threads(all_threads)
+        h0 = time.perf_counter()
+        O.pcg(P1, max_iter=100, rtol=0.0)
+        extra["c1_pcg_100_iterations_seconds"] = round(time.perf_counter() - h0, 4)
+        if (a.n, a.N) == (32, 10):
+            # 10 iterations (a bounded sample), reported per iteration
+            P2 = O.setup(brick)
+            h0 = time.perf_counter()
+            O.pcg(P2, max_iter=10, rtol=0.0)
+            extra["c2_pcg_seconds_per_iteration"] = round((time.perf_counter() - h0) / 10, 4)
+            del P2
+        out["cpu_baseline"]["extra"] = extra
+        log(f"cpu oracle extra: {extra}")
 
     print(json.dumps(out), flush=True)
 
