@@ -192,7 +192,8 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
                 // measured 1.3-1.6x faster at N = 12-14; N = 15 runs faster
                 // without)
                 int off = k * N2 + tc;
-                if constexpr (sizeof(T) == sizeof(double) && N >= 11 && N != 15)
+                if constexpr ((sizeof(T) == sizeof(double) && N >= 11 && N != 15) ||
+                              (sizeof(T) == sizeof(float) && N >= 13))
                     asm volatile("" : "+v"(off) : "v"(wt[k - 1]));
                 const GT *gp = Ge + off;
                 g1 = ax_ldg<T>(gp); g2 = ax_ldg<T>(gp + N3); g3 = ax_ldg<T>(gp + 2 * N3);
