@@ -70,6 +70,19 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
+def device_record(torch):
+    """What the runtime reports about the GPU (to confirm the nominal
+    figures the roofline uses)."""
+    p = torch.cuda.get_device_properties(0)
+    rec = {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+           "compute_units": p.multi_processor_count,
+           "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+    for k in ("L2_cache_size", "clock_rate", "memory_clock_rate", "memory_bus_width"):
+        if hasattr(p, k):
+            rec[k] = getattr(p, k)
+    return rec
+
+
 def traffic_record(kernel_hash):
     """Counter-measured HBM bytes per AX launch, if profiles/ holds a record
     taken on the current kernel source."""
@@ -216,6 +229,7 @@ def main():
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "ax_reduced_precision": variants,
+        "device": device_record(torch),
     })
     del u, w, G, bm
     torch.cuda.empty_cache()

@@ -1,4 +1,4 @@
-"""Pins for the oracle's AX operator (Section II-B, Listing 1).
+"""Pins for the oracle's AX operator (Section II-B).
 
 (a) against the dense Kronecker element matrix built by brute force;
 (b) invariants: AX(const) = 0, symmetry, positive semi-definiteness;
