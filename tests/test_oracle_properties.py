@@ -7,7 +7,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 hyp = pytest.importorskip("hypothesis")
-from hypothesis import given, settings, HealthCheck  # noqa: E402
+from hypothesis import assume, given, settings, HealthCheck  # noqa: E402
 from hypothesis import strategies as st  # noqa: E402
 
 import oracle as O  # noqa: E402
@@ -43,7 +43,8 @@ def test_operator_invariants_on_deformed_bricks(N, dims, d, seed):
         return
     xi, wq = O.gll(N)
     D = O.deriv(N, xi)
-    G, _, _ = O.geom(N, D, wq, *O.brick_coords(b, xi))
+    G, _, jmin = O.geom(N, D, wq, *O.brick_coords(b, xi))
+    assume(jmin > 0)            # a valid (non-inverted) isoparametric map
     u = S.uniform_field(b.E, N, seed=seed)
     v = S.uniform_field(b.E, N, seed=seed + 1)
     Au, Av = O.ax(u, G, D), O.ax(v, G, D)
@@ -74,6 +75,9 @@ def test_dssum_equals_scatter_matrix(N, dims, d, seed):
 def test_pcg_reaches_the_direct_solution(N, dims, d):
     b = S.Brick(*dims, N, d)
     P = O.setup(b)
+    # an under-resolved deformation can invert the degree N-1 map (then the
+    # operator is indefinite and PCG rightly reports breakdown)
+    assume(P.jmin > 0)
     res = O.pcg(P, max_iter=4000, rtol=1e-12)
     assert res.state == 1
     # the assembled system on the free global nodes, solved directly
