@@ -162,6 +162,20 @@ def main():
         c1.record(stream)
         torch.cuda.synchronize()
         copy_gbs = 2 * 8 * n_copy * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        # two more references: non-temporal copy and a read-only stream
+        refs = {}
+        sink = torch.zeros(1, dtype=torch.float64, device=dev)
+        for mode, name, factor in ((0, "copy_nt_gbs", 2), (1, "read_gbs", 1)):
+            for _ in range(3):
+                nbx.stream_f64(mode, src, dst, sink)
+            c0.record(stream)
+            for _ in range(10):
+                nbx.stream_f64(mode, src, dst, sink)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            refs[name] = round(factor * 8 * n_copy * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9, 1)
+        log(f"references: non-temporal copy {refs['copy_nt_gbs']:.0f} GB/s, "
+            f"read-only {refs['read_gbs']:.0f} GB/s")
         del src, dst
         log(f"copy: {copy_gbs:.0f} GB/s")
 
@@ -227,7 +241,9 @@ def main():
                      "mean_launch_us": round(mean_launch * 1e6, 2),
                      "median_launch_us": round(statistics.median(per) * 1e6, 2),
                      "copy_gbs": round(copy_gbs, 1),
-                     "frac_of_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_copy": round(achieved / copy_gbs, 4),
+                     **refs,
+                     "frac_of_read": round(achieved / refs["read_gbs"], 4)},
         "ax_reduced_precision": variants,
         "device": device_record(torch),
     })

@@ -65,6 +65,14 @@ int nbx_version(void);
  * overlap. */
 int nbx_copy_f64(const double *src, double *dst, int64_t n, void *stream);
 
+/* Further achievable-bandwidth references over n doubles (n even), one
+ * 16-byte vector per lane with non-temporal accesses: mode 0 copies src to
+ * dst; mode 1 only reads src (sink, one device double, is written only in
+ * an impossible case, so no bytes are stored).  Async.  NBX_EINVAL for odd
+ * n, another mode or null pointers. */
+int nbx_stream_f64(int mode, const double *src, double *dst, int64_t n, double *sink,
+                   void *stream);
+
 /* ------------------------------------------------------------ set-up --
  * The paper names the geometry ("block or linear geometry", Section II-B)
  * but not its discretisation; these calls build it with the standard

@@ -64,6 +64,7 @@ def lib():
         "nbx_last_hip_error": ([], i32),
         "nbx_version": ([], i32),
         "nbx_copy_f64": ([vp, vp, i64, vp], i32),
+        "nbx_stream_f64": ([i32, vp, vp, i64, vp, vp], i32),
         "nbx_gll": ([i32, vp, vp], i32),
         "nbx_deriv": ([i32, vp], i32),
         "nbx_geom_brick": ([i32, i32, i32, i32, vp, vp, vp, vp, vp], i32),
@@ -182,6 +183,21 @@ def copy_f64(src, dst, stream=None):
 
 
 # ----------------------------------------------------------------- set-up
+
+def stream_f64(mode: int, src, dst=None, sink=None, stream=None):
+    """Bandwidth references (nbx_stream_f64): mode 0 non-temporal copy
+    src -> dst, mode 1 read-only stream over src."""
+    torch = _torch()
+    n = src.numel()
+    if mode == 0:
+        _need(dst, n, "dst")
+    if mode == 1 and sink is None:
+        sink = torch.zeros(1, dtype=torch.float64, device=src.device)
+    _check(lib().nbx_stream_f64(mode, _dptr(src, torch.float64, "src"),
+                                _dptr(dst, torch.float64, "dst") if mode == 0 else None, n,
+                                _dptr(sink, torch.float64, "sink") if mode == 1 else None,
+                                _stream(stream)), "nbx_stream_f64")
+
 
 def gll(N: int):
     xi = np.zeros(N); w = np.zeros(N)
