@@ -455,3 +455,20 @@ def test_pcg_tiny_elements(N):
     x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=3000, check_every=3)
     assert r.status == 0 and abs(r.iters - ora.iters) <= 1
     assert rel(host(x), ora.x) <= 1e-8
+
+
+def test_bandwidth_reference_streams():
+    """nbx_copy_f64 / nbx_stream_f64: the copies are exact, the read-only
+    stream stores nothing, odd lengths are refused."""
+    src = torch.randn(1 << 20, dtype=torch.float64, device=DEV)
+    dst = torch.zeros_like(src)
+    nbx.copy_f64(src, dst)
+    assert torch.equal(src, dst)
+    dst.zero_()
+    nbx.stream_f64(0, src, dst)
+    assert torch.equal(src, dst)
+    sink = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nbx.stream_f64(1, src, sink=sink)
+    assert host(sink)[0] == 0.0
+    with pytest.raises(nbx.NbxError):
+        nbx.stream_f64(1, src[:-1], sink=sink)
