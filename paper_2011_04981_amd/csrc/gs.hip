@@ -17,24 +17,23 @@
 namespace nbx {
 namespace {
 
+// Threads [0, n_groups) sum one shared group each; with apply_mask the
+// threads after them zero the unshared Dirichlet nodes (one launch for
+// both steps).
 template <typename T>
 __global__ void dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off,
                              const int32_t *__restrict__ idx, const uint8_t *__restrict__ gflag,
-                             T *__restrict__ v, int apply_mask, const double *__restrict__ flag)
+                             T *__restrict__ v, int apply_mask, int32_t n_mask,
+                             const int32_t *__restrict__ mask_idx,
+                             const double *__restrict__ flag)
 {
     if (flag && *flag != 0.0) return;   // uniform: solve already finished
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_groups) return;
-    dssum_group<T>(g, off, idx, gflag, v, apply_mask);
-}
-
-template <typename T>
-__global__ void mask_only_kernel(int32_t n, const int32_t *__restrict__ idx, T *__restrict__ v,
-                                 const double *__restrict__ flag)
-{
-    if (flag && *flag != 0.0) return;
-    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) v[idx[q]] = 0;
+    if (g < n_groups) {
+        dssum_group<T>(g, off, idx, gflag, v, apply_mask);
+    } else if (apply_mask && g - n_groups < n_mask) {
+        v[mask_idx[g - n_groups]] = 0;
+    }
 }
 
 __global__ void multiplicity_kernel(int64_t n, const uint8_t *__restrict__ info,
@@ -69,14 +68,11 @@ void free_plan(GsPlan &p)
 template <typename T>
 int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const double *flag)
 {
-    if (gs.n_groups > 0) {
-        hipLaunchKernelGGL(dssum_kernel<T>, dim3((gs.n_groups + 255) / 256), dim3(256), 0, s,
-                           gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask, flag);
-        NBX_LAUNCH_CHECK();
-    }
-    if (apply_mask && gs.n_mask_only > 0) {
-        hipLaunchKernelGGL(mask_only_kernel<T>, dim3((gs.n_mask_only + 255) / 256), dim3(256),
-                           0, s, gs.n_mask_only, gs.mask_idx, v, flag);
+    const int64_t nt = (int64_t)gs.n_groups + (apply_mask ? gs.n_mask_only : 0);
+    if (nt > 0) {
+        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
+                           gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask,
+                           gs.n_mask_only, gs.mask_idx, flag);
         NBX_LAUNCH_CHECK();
     }
     return NBX_OK;
