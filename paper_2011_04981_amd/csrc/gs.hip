@@ -28,7 +28,12 @@ __global__ void dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off,
                              const double *__restrict__ flag)
 {
     if (flag && *flag != 0.0) return;   // uniform: solve already finished
-    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-aware mapping: workgroups are dealt to the 8 XCDs round-robin, so
+    // give each XCD a contiguous range of groups (neighbouring groups share
+    // cache lines; each XCD has its own L2)
+    const int32_t per = (int32_t)(gridDim.x / 8);
+    const int32_t vb = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    const int32_t g = vb * blockDim.x + threadIdx.x;
     if (g < n_groups) {
         dssum_group<T>(g, off, idx, gflag, v, apply_mask);
     } else if (apply_mask && g - n_groups < n_mask) {
@@ -70,7 +75,8 @@ int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const do
 {
     const int64_t nt = (int64_t)gs.n_groups + (apply_mask ? gs.n_mask_only : 0);
     if (nt > 0) {
-        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
+        const int64_t nb = ((nt + 255) / 256 + 7) / 8 * 8;   // a multiple of the 8 XCDs
+        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)nb), dim3(256), 0, s,
                            gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask,
                            gs.n_mask_only, gs.mask_idx, flag);
         NBX_LAUNCH_CHECK();
