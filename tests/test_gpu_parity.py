@@ -472,3 +472,21 @@ def test_bandwidth_reference_streams():
     assert host(sink)[0] == 0.0
     with pytest.raises(nbx.NbxError):
         nbx.stream_f64(1, src[:-1], sink=sink)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_indefinite_operator_reports_breakdown(prec):
+    """Negated factors make A negative definite: <p, Ap> < 0 at the first
+    step.  Every solver must stop at once with the breakdown status (the
+    mixed ones after their FP64 fallback has broken down too), not hang or
+    return a bogus converged state."""
+    b = S.scaled_c2_brick(2, 5)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    Gneg = -st.G
+    P = nbx.Problem(Gneg, st.D, b.N, st.gs)
+    p = {"f64": nbx.F64, "f32": nbx.F32, "f16": nbx.F16}[prec]
+    x, r = P.pcg(st.b, rtol=1e-10, max_iter=500, prec=p, check_every=5)
+    print(f"{prec}: status {r.status}, flag {r.flag}, iters {r.iters}, fell back {r.fell_back}")
+    assert r.status == -5 and r.flag == 2
+    assert r.iters <= 5
+    assert np.all(np.isfinite(host(x)))
