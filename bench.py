@@ -210,6 +210,35 @@ def main():
             log(f"AX {name}: {t*1e6:.1f} us, {gbs:.0f} GB/s")
         del u32, w32, G32, G16f, gsf, G16b, gsb
 
+        # ---- host -> device transfer of the operator's inputs (G and u) from
+        # pinned host memory, against the AX time: how many applications one
+        # transfer must serve to be negligible (the library itself builds G
+        # on the device, so no transfer is on any timed path)
+        transfer = None
+        if not a.no_ax_variants:
+            hG = torch.empty(G.shape, dtype=G.dtype, pin_memory=True)
+            hu = torch.empty(u.shape, dtype=u.dtype, pin_memory=True)
+            dG = torch.empty_like(G)
+            du = torch.empty_like(u)
+            dG.copy_(hG, non_blocking=True)
+            du.copy_(hu, non_blocking=True)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                dG.copy_(hG, non_blocking=True)
+                du.copy_(hu, non_blocking=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_h2d = e0.elapsed_time(e1) * 1e-3 / 3
+            nbytes = (G.numel() + u.numel()) * 8
+            transfer = {"bytes": nbytes, "seconds": round(t_h2d, 5),
+                        "gbs": round(nbytes / t_h2d / 1e9, 1),
+                        "ax_applications_per_transfer": round(t_h2d / mean_launch, 1)}
+            log(f"H2D of G and u: {t_h2d*1e3:.1f} ms = {transfer['gbs']:.0f} GB/s "
+                f"= {transfer['ax_applications_per_transfer']:.0f} AX applications")
+            del hG, hu, dG, du
+
     ax_hash = src_hash("ax_kernel.hpp", "ax_f64.hip", "ax.hip")
     achieved = abytes / mean_launch / 1e9
     tb = traffic_record(ax_hash) if (N, E) == (10, 32768) else None
@@ -245,6 +274,7 @@ def main():
                      **refs,
                      "frac_of_read": round(achieved / refs["read_gbs"], 4)},
         "ax_reduced_precision": variants,
+        "host_to_device": transfer,
         "device": device_record(torch),
     })
     del u, w, G, bm
