@@ -100,6 +100,16 @@ int nbx_geom_brick(int ex, int ey, int ez, int N, const double *deform_host,
  * async).  bm may be NULL. */
 int nbx_geom(const double *xyz, int N, int64_t E, double *G, double *bm, void *stream);
 
+/* Repacks geometric factors given in the layout of the operator's g
+ * argument (Section II-B: g(6, N^3, E), the six factors of a node
+ * contiguous, g_aos[(e*N^3 + p)*6 + f]) into the [E][6][N^3] layout every
+ * other call takes (g_soa[(e*6 + f)*N^3 + p]), f = 0..5 for g1..g6.
+ * Device arrays of 6*E*N^3 doubles each, caller-owned; they must not
+ * overlap (NBX_EINVAL).  Async on stream, no allocation; E = 0 is a no-op.
+ * NBX_EINVAL for N outside [2, 16], E < 0 or a null pointer. */
+int nbx_repack_g_aos_to_soa(const double *g_aos, double *g_soa, int N, int64_t E,
+                            void *stream);
+
 /* Global node ids of the brick's local nodes (gid_host[E*N^3]) and the
  * homogeneous Dirichlet flags (bnd_host[E*N^3] = 1 on the cube's
  * boundary).  Host only. */

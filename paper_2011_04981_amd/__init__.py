@@ -86,6 +86,7 @@ def lib():
         "nbx_problem_create": ([vp, vp, i32, i64, vp, C.POINTER(vp), vp], i32),
         "nbx_problem_destroy": ([vp], i32),
         "nbx_problem_dinv": ([vp, vp, vp], i32),
+        "nbx_repack_g_aos_to_soa": ([vp, vp, i32, i64, vp], i32),
         "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "nbx_pcg_default_opts": ([C.POINTER(PcgOpts)], None),
         "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
@@ -243,6 +244,23 @@ def geom(xyz, N: int, stream=None):
     _check(lib().nbx_geom(_dptr(xyz, torch.float64, "xyz"), N, E, _dptr(G), _dptr(bm),
                           _stream(stream)), "nbx_geom")
     return G, bm
+
+
+def repack_g_aos_to_soa(g_aos, N: int, out=None, stream=None):
+    """Geometric factors in the layout of the operator's g argument,
+    g(6, N^3, E) with the factor fastest (a float64 tensor of E*N^3*6 values,
+    e.g. shaped [E, N^3, 6]), repacked on the device into [E, 6, N^3]."""
+    torch = _torch()
+    n6 = g_aos.numel()
+    if n6 % (6 * N ** 3):
+        raise ValueError("g_aos must hold 6 factors for every node of whole elements")
+    E = n6 // (6 * N ** 3)
+    out = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=g_aos.device) \
+        if out is None else _need(out, n6, "out")
+    _check(lib().nbx_repack_g_aos_to_soa(_dptr(g_aos, torch.float64, "g_aos"),
+                                         _dptr(out, torch.float64, "out"), N, E,
+                                         _stream(stream)), "nbx_repack_g_aos_to_soa")
+    return out
 
 
 def brick_ids(ex: int, ey: int, ez: int, N: int):

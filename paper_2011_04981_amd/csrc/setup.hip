@@ -210,6 +210,31 @@ __global__ void sine_source_kernel(int64_t n, const double *__restrict__ xyz,
            sin(M_PI * xyz[2 * n + l]);
 }
 
+// g(6, N^3, E) with the factor index fastest (the layout of the operator's
+// g argument in Section II-B) to [E][6][N^3]: a block stages 256 nodes'
+// six factors, contiguous in the source, in LDS and writes them factor by
+// factor, consecutive nodes of one factor being contiguous in the target.
+constexpr int kRepackNodes = 256;
+
+__global__ void __launch_bounds__(kRepackNodes)
+repack_g_kernel(int64_t n, int N3, const double *__restrict__ src, double *__restrict__ dst)
+{
+    __shared__ double s[6 * kRepackNodes + 6];
+    const int64_t l0 = (int64_t)blockIdx.x * kRepackNodes;
+    const int64_t left = n - l0;
+    const int cnt = left < kRepackNodes ? (int)left : kRepackNodes;
+    for (int q = threadIdx.x; q < 6 * cnt; q += kRepackNodes)
+        s[q] = __builtin_nontemporal_load(src + 6 * l0 + q);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        const int64_t l = l0 + threadIdx.x;
+        const int64_t e = l / N3, p = l - e * N3;
+        double *d = dst + e * 6 * N3 + p;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) __builtin_nontemporal_store(s[6 * threadIdx.x + f], d + f * N3);
+    }
+}
+
 int make_tab(int N, GllTab &tab)
 {
     int st = gll_host(N, tab.xi, tab.w);
@@ -305,6 +330,25 @@ extern "C" int nbx_geom(const double *xyz, int N, int64_t E, double *G, double *
     BrickDesc b{};
     b.ex = b.ey = b.ez = 1;
     return geom_launch(N, E, b, xyz, G, bm, nullptr, as_stream(stream));
+}
+
+extern "C" int nbx_repack_g_aos_to_soa(const double *g_aos, double *g_soa, int N, int64_t E,
+                                       void *stream)
+{
+    if (N < 2 || N > kMaxN || E < 0) return NBX_EINVAL;
+    if (E == 0) return NBX_OK;
+    if (!g_aos || !g_soa) return NBX_EINVAL;
+    const int N3 = N * N * N;
+    const int64_t n = E * N3;
+    if ((n + kRepackNodes - 1) / kRepackNodes > 0x7fffffffLL) return NBX_EUNSUPPORTED;
+    // the two arrays must not overlap
+    const uintptr_t a = (uintptr_t)g_aos, b = (uintptr_t)g_soa,
+                    bytes = (uintptr_t)(6 * n) * sizeof(double);
+    if (a < b + bytes && b < a + bytes) return NBX_EINVAL;
+    hipLaunchKernelGGL(repack_g_kernel, dim3((unsigned)((n + kRepackNodes - 1) / kRepackNodes)),
+                       dim3(kRepackNodes), 0, as_stream(stream), n, N3, g_aos, g_soa);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
 }
 
 extern "C" int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host,

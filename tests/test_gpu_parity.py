@@ -490,3 +490,21 @@ def test_indefinite_operator_reports_breakdown(prec):
     assert r.status == -5 and r.flag == 2
     assert r.iters <= 5
     assert np.all(np.isfinite(host(x)))
+
+
+@pytest.mark.parametrize("N,E", [(2, 1), (3, 7), (10, 33), (16, 3)])
+def test_repack_paper_factor_layout(N, E):
+    """nbx_repack_g_aos_to_soa: factors in the layout of the operator's g
+    argument, g(6, N^3, E) with the factor fastest, into [E][6][N^3] bit for
+    bit (node counts below, at and off the kernel's 256-node blocks)."""
+    G = cuda(S.random_factors(E, N, seed=41))            # [E, 6, N^3]
+    aos = G.permute(0, 2, 1).contiguous()                # [E, N^3, 6]
+    soa = nbx.repack_g_aos_to_soa(aos, N)
+    assert torch.equal(soa, G)
+    out = torch.full_like(G, float("nan"))
+    nbx.repack_g_aos_to_soa(aos, N, out=out)
+    assert torch.equal(out, G)
+    with pytest.raises(nbx.NbxError):                    # overlapping arrays
+        nbx.repack_g_aos_to_soa(aos, N, out=aos)
+    empty = torch.empty((0, N ** 3, 6), dtype=torch.float64, device=DEV)
+    assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 6, N ** 3)
