@@ -354,12 +354,43 @@ def main():
                 per1.append((e0, e1))
             torch.cuda.synchronize()
             t1 = statistics.median(s_.elapsed_time(e_) * 1e-3 for s_, e_ in per1)
+            # back to back: 200 launches between two events (per-launch
+            # events above also time the host's submission gaps)
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(200):
+                nbx.ax(u1, st1.G, st1.D, out=w1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t1b = e0.elapsed_time(e1) * 1e-3 / 200
+            # cold: a 512 MB copy before each launch evicts the 4 MB working
+            # set from L2 and MALL
+            fa = torch.empty(64 << 20, dtype=torch.float64, device=dev)
+            fb = torch.empty_like(fa)
+            per1c = []
+            for _ in range(20):
+                nbx.copy_f64(fa, fb)
+                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                nbx.ax(u1, st1.G, st1.D, out=w1)
+                e1.record(stream)
+                per1c.append((e0, e1))
+            torch.cuda.synchronize()
+            t1c = statistics.median(s_.elapsed_time(e_) * 1e-3 for s_, e_ in per1c)
+            del fa, fb
             st1.problem.pcg(st1.b, max_iter=100, fixed_iters=1, check_every=20)
             _, r1 = st1.problem.pcg(st1.b, max_iter=100, fixed_iters=1, check_every=20)
             out["c1"] = {"E": c1.E, "N": 10, "ax_median_us": round(t1 * 1e6, 2),
                          "ax_gflops": round(nbx.ax_flops(10, c1.E) / t1 / 1e9, 1),
+                         "ax_caches": "warm (repeated launches on a 4 MB working set)",
+                         "ax_back_to_back_us": round(t1b * 1e6, 2),
+                         "ax_back_to_back_gflops": round(nbx.ax_flops(10, c1.E) / t1b / 1e9, 1),
+                         "ax_cold_median_us": round(t1c * 1e6, 2),
+                         "ax_cold_gflops": round(nbx.ax_flops(10, c1.E) / t1c / 1e9, 1),
                          "pcg_100_iterations_seconds": round(r1.seconds, 5)}
-            log(f"C1: AX {t1*1e6:.1f} us, 100 PCG iterations {r1.seconds*1e3:.2f} ms")
+            log(f"C1: AX {t1*1e6:.1f} us warm, {t1b*1e6:.1f} us back to back, "
+                f"{t1c*1e6:.1f} us cold, "
+                f"100 PCG iterations {r1.seconds*1e3:.2f} ms")
             del st1, u1, w1
 
     # ---- the same mesh at N = 8 and 12: FP64 PCG against the refinement
