@@ -151,11 +151,14 @@ int nbx_pcg_get_tile(int prec, int N);
  * work (Section V); G is 48 of AX's 64 bytes per node in FP64.
  *
  * nbx_g16_pack: per element e, gscale[e] = 2^(floor(log2 m_e) - 14) with
- * m_e = max |G_e| (1 if G_e is zero), and G16[e][f][q] = the 16-bit word of
- * round(round32(G[e][f][q] / gscale[e])), both roundings to nearest-even,
- * first to FP32, then to gprec = NBX_F16 (IEEE binary16) or NBX_BF16
- * (bfloat16).  G (FP64, [E][6][N^3]), G16 ([E][6][N^3] 16-bit words) and
- * gscale ([E] float) are device arrays.  Async.
+ * m_e = max |G_e| (1 if G_e is zero), and the 16-bit word of factor f at
+ * node q, round(round32(G[e][f][q] / gscale[e])) with both roundings to
+ * nearest-even, first to FP32, then to gprec = NBX_F16 (IEEE binary16) or
+ * NBX_BF16 (bfloat16), stored at G16[((e*3 + f/2)*N^3 + q)*2 + f%2]: three
+ * planes per element of 32-bit words holding the factor pairs (g1,g2),
+ * (g3,g4), (g5,g6) of a node, low half first.  G (FP64, [E][6][N^3]), G16
+ * (6*E*N^3 16-bit words, 4-byte aligned) and gscale ([E] float) are device
+ * arrays.  Async.
  *
  * nbx_ax_g16: w = AX(u) in FP32 arithmetic with the factors
  * gscale[e] * G16_e (u, w float [E][N^3]); bit-identical to FP32 AX with

@@ -301,13 +301,14 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[in
 
 
 def g16_pack(G, N: int, gprec: int, stream=None):
-    """(G16 [E, 6, N^3] int16 words, gscale [E] float32): the factors in
+    """(G16 [E, 3, N^3, 2] int16 words, gscale [E] float32): the factors in
     16-bit storage (gprec F16 or BF16) with per-element power-of-two
-    scales (nbx_g16_pack)."""
+    scales, as factor pairs (g1,g2), (g3,g4), (g5,g6) per node
+    (nbx_g16_pack)."""
     torch = _torch()
     E = G.numel() // (6 * N ** 3)
     _need(G, 6 * E * N ** 3, "G")
-    G16 = torch.empty((E, 6, N ** 3), dtype=torch.int16, device=G.device)
+    G16 = torch.empty((E, 3, N ** 3, 2), dtype=torch.int16, device=G.device)
     gs = torch.empty(E, dtype=torch.float32, device=G.device)
     _check(lib().nbx_g16_pack(gprec, _dptr(G, torch.float64, "G"), N, E, _dptr(G16),
                               _dptr(gs), _stream(stream)), "nbx_g16_pack")
@@ -320,7 +321,7 @@ def ax_g16(u, G16, gscale, D, gprec: int, out=None, stream=None):
     N = D.shape[0]
     E = u.numel() // N ** 3
     if u.numel() != E * N ** 3 or G16.numel() != 6 * u.numel() or gscale.numel() != E:
-        raise ValueError("u [E, N^3], G16 [E, 6, N^3] and gscale [E] must agree")
+        raise ValueError("u [E, N^3], G16 [E, 3, N^3, 2] and gscale [E] must agree")
     _need(D, N * N, "D")
     w = torch.empty_like(u) if out is None else out
     if w.numel() != u.numel():

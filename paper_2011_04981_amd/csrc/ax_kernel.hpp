@@ -79,6 +79,20 @@ __device__ inline T ax_ldg(const GT *p)
         return (T)__builtin_nontemporal_load(p);
     }
 }
+// A 32-bit word of 16-bit storage: the node's factors 2h (low half) and
+// 2h+1 (high half), widened to FP32.
+template <typename GT>
+__device__ inline void ax_half2(uint32_t wd, float &lo, float &hi)
+{
+    if constexpr (std::is_same<GT, g_f16>::value) {
+        lo = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd & 0xffffu));
+        hi = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd >> 16));
+    } else {
+        lo = __uint_as_float(wd << 16);
+        hi = __uint_as_float(wd & 0xffff0000u);
+    }
+}
+
 template <typename T>
 __device__ inline void ax_st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 // Fused multiply-add written out: every instantiation (tile, fused or not)
@@ -94,7 +108,8 @@ __device__ inline float ax_fma(float a, float b, float c) { return __builtin_fma
 // operator instance (blockIdx.x for a single operator; a table entry when
 // one launch serves several independent problems).
 // GT is the storage type of G (T, or g_f16 / g_bf16 with T = float); for
-// 16-bit storage G_e holds G_e / gscale[e] (gscale[e] a power of two) and
+// 16-bit storage G_e holds G_e / gscale[e] (gscale[e] a power of two) in
+// three planes of factor pairs (see ax_half2), and
 // the element's result is multiplied by gscale[e], which in FP32 is exact
 // and commutes with every rounding of the element's arithmetic.
 template <typename T, int N, int EPB, bool PCG, typename GT = T>
@@ -149,10 +164,20 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
     // factor-major order: consecutive requests cover consecutive addresses,
     // so a line shared by two 8N^2-byte slabs is asked for twice in a row
     T g[6][PF];
+    if constexpr (kHalfG) {
+        const uint32_t *Gw = reinterpret_cast<const uint32_t *>(Ge);   // 3 N^3 words
 #pragma unroll
-    for (int f = 0; f < 6; ++f)
+        for (int h = 0; h < 3; ++h)
 #pragma unroll
-        for (int k = 0; k < PF; ++k) g[f][k] = ax_ldg<T>(Ge + f * N3 + k * N2 + tc);
+            for (int k = 0; k < PF; ++k)
+                ax_half2<GT>(__builtin_nontemporal_load(Gw + h * N3 + k * N2 + tc), g[2 * h][k],
+                             g[2 * h + 1][k]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int k = 0; k < PF; ++k) g[f][k] = ax_ldg<T>(Ge + f * N3 + k * N2 + tc);
+    }
     for (int q = t; q < N2; q += NT) s_D[q] = (T)Dg[q];
     if constexpr (PCG) {
         if (valid) {
@@ -195,10 +220,17 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
                 if constexpr ((sizeof(T) == sizeof(double) && N >= 11 && N != 15) ||
                               (sizeof(T) == sizeof(float) && N >= 13))
                     asm volatile("" : "+v"(off) : "v"(wt[k - 1]));
-                const GT *gp = Ge + off;
-                g1 = ax_ldg<T>(gp); g2 = ax_ldg<T>(gp + N3); g3 = ax_ldg<T>(gp + 2 * N3);
-                g4 = ax_ldg<T>(gp + 3 * N3); g5 = ax_ldg<T>(gp + 4 * N3);
-                g6 = ax_ldg<T>(gp + 5 * N3);
+                if constexpr (kHalfG) {
+                    const uint32_t *gw = reinterpret_cast<const uint32_t *>(Ge) + off;
+                    ax_half2<GT>(__builtin_nontemporal_load(gw), g1, g2);
+                    ax_half2<GT>(__builtin_nontemporal_load(gw + N3), g3, g4);
+                    ax_half2<GT>(__builtin_nontemporal_load(gw + 2 * N3), g5, g6);
+                } else {
+                    const GT *gp = Ge + off;
+                    g1 = ax_ldg<T>(gp); g2 = ax_ldg<T>(gp + N3); g3 = ax_ldg<T>(gp + 2 * N3);
+                    g4 = ax_ldg<T>(gp + 3 * N3); g5 = ax_ldg<T>(gp + 4 * N3);
+                    g6 = ax_ldg<T>(gp + 5 * N3);
+                }
             }
             const T wr = ax_fma(g3, ut, ax_fma(g2, us, g1 * ur));
             const T ws = ax_fma(g5, ut, ax_fma(g4, us, g2 * ur));

@@ -10,7 +10,10 @@
 // Each value is rounded to nearest-even twice, FP64 -> FP32 -> 16 bits
 // (IEEE binary16 or bfloat16).  AX multiplies the element's FP32 result by
 // gscale[e]; a power-of-two scale is exact, so this equals AX with the
-// dequantised factors.
+// dequantised factors.  Storage: per element three planes of 32-bit words,
+// plane h holding factors 2h and 2h+1 of each node in its low and high half
+// ([E][3][N^3][2] 16-bit words), so that AX fetches a node's six factors
+// with three 4-byte loads instead of six 2-byte ones.
 #include "internal.hpp"
 
 #include <cmath>
@@ -26,11 +29,18 @@ __device__ inline uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+__device__ inline uint16_t to16(int bf16, double v)
+{
+    const float f = (float)v;
+    return bf16 ? f32_to_bf16_rne(f) : __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
 // one block per element: max |G_e|, the scale, then the packed words
 __global__ void __launch_bounds__(256)
-g16_pack_kernel(int bf16, int n6, const double *__restrict__ G, uint16_t *__restrict__ G16,
+g16_pack_kernel(int bf16, int N3, const double *__restrict__ G, uint32_t *__restrict__ G16,
                 float *__restrict__ gscale)
 {
+    const int n6 = 6 * N3;
     __shared__ double s_max[4];
     const int64_t e = blockIdx.x;
     const double *Ge = G + (size_t)e * n6;
@@ -45,10 +55,12 @@ g16_pack_kernel(int bf16, int n6, const double *__restrict__ G, uint16_t *__rest
     if (m > 0.0 && isfinite(m)) { frexp(m, &ex); ex -= 15; }   // m = f 2^ex', f in [0.5,1)
     const double inv = ldexp(1.0, -ex);
     if (threadIdx.x == 0) gscale[e] = ldexpf(1.0f, ex);
-    uint16_t *out = G16 + (size_t)e * n6;
-    for (int q = threadIdx.x; q < n6; q += blockDim.x) {
-        const float f = (float)(Ge[q] * inv);
-        out[q] = bf16 ? f32_to_bf16_rne(f) : __builtin_bit_cast(uint16_t, (_Float16)f);
+    uint32_t *out = G16 + (size_t)e * 3 * N3;
+    for (int q = threadIdx.x; q < 3 * N3; q += blockDim.x) {
+        const int h = q / N3, p = q - h * N3;
+        const uint32_t lo = to16(bf16, Ge[(2 * h) * N3 + p] * inv);
+        const uint32_t hi = to16(bf16, Ge[(2 * h + 1) * N3 + p] * inv);
+        out[q] = lo | (hi << 16);
     }
 }
 
@@ -66,7 +78,7 @@ extern "C" int nbx_g16_pack(int gprec, const double *G, int N, int64_t E, void *
     if (!G || !G16 || !gscale) return NBX_EINVAL;
     if (E > 0x7fffffffLL) return NBX_EUNSUPPORTED;
     hipLaunchKernelGGL(g16_pack_kernel, dim3((unsigned)E), dim3(256), 0, as_stream(stream),
-                       gprec == NBX_BF16 ? 1 : 0, 6 * N * N * N, G, (uint16_t *)G16, gscale);
+                       gprec == NBX_BF16 ? 1 : 0, N * N * N, G, (uint32_t *)G16, gscale);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
 }

@@ -52,10 +52,12 @@ def _factors(E, N, seed):
 def test_pack_bit_exact(fmt, N, E):
     G = _factors(E, N, seed=N)
     G[1] = 0.0                                         # an all-zero element
-    words, gs = g16.pack(G, N, fmt)
+    words, gs = g16.pack(G, N, fmt)                   # [E, 6, N^3]
     w_gpu, gs_gpu = nbx.g16_pack(cuda(G), N, FMT[fmt])
     assert np.array_equal(host(gs_gpu), gs)
-    assert np.array_equal(host(w_gpu).view(np.uint16), words)
+    # the library stores factor pairs (g1,g2), (g3,g4), (g5,g6) per node
+    pairs = words.reshape(E, 3, 2, N ** 3).transpose(0, 1, 3, 2)
+    assert np.array_equal(host(w_gpu).view(np.uint16), pairs)
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
