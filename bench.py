@@ -434,7 +434,8 @@ def main():
             for Er in (800, 8000):
                 Nr = 16
                 ur = torch.as_tensor(S.uniform_field(Er, Nr, seed=0)).to(dev)
-                Gr = torch.as_tensor(S.random_factors(Er, Nr, seed=1)).to(dev)
+                Gr = nbx.pair_factors(torch.as_tensor(S.random_factors(Er, Nr, seed=1)).to(dev),
+                                      Nr)
                 Dr = nbx.deriv_device(Nr, dev)
                 wr = torch.empty_like(ur)
                 for _ in range(20):

@@ -22,8 +22,15 @@
  *
  * Layouts (Section II-B, Listing 1, column-major u(i,j,k,e)):
  *   u, w, vectors : [E][N][N][N], i fastest: u[((e*N + k)*N + j)*N + i]
- *   G             : [E][6][N^3]; factor f holds g_(f+1) of the listing, the
- *                   symmetric matrix [[g1,g2,g3],[g2,g4,g5],[g3,g5,g6]]
+ *   G             : per element three planes of factor pairs, (g1,g2),
+ *                   (g3,g4), (g5,g6), one pair per node: factor f (0-based,
+ *                   g_(f+1) of the listing, the symmetric matrix
+ *                   [[g1,g2,g3],[g2,g4,g5],[g3,g5,g6]]) of node q of
+ *                   element e at G[((e*3 + f/2)*N^3 + q)*2 + f%2], written
+ *                   [E][3][N^3][2] below (6*E*N^3 values).  A lane of the
+ *                   operator fetches a pair with one 16-byte load.
+ *                   nbx_pair_factors converts from [E][6][N^3] planes,
+ *                   nbx_repack_g_aos_to_soa from the listing's g(6,N^3,E).
  *   D             : N x N row-major, D[a*N + b] = l_b'(xi_a) (the
  *                   listing's dxm1; its transpose dxtm1 is derived inside)
  *   N             : Gauss-Lobatto-Legendre nodes per direction (degree N-1),
@@ -90,7 +97,7 @@ int nbx_deriv(int N, double *D_host);
  * deform_host[12] = {A_x,k1,k2,k3, A_y,k1,k2,k3, A_z,k1,k2,k3}: coordinate
  * c of the node at undeformed position (X,Y,Z) is
  * C + A_c sin(k1 pi X) sin(k2 pi Y) sin(k3 pi Z).  Outputs (device):
- * G[E][6][N^3] = w_i w_j w_k det(J) (grad r_a . grad r_b) from
+ * G[E][3][N^3][2] = w_i w_j w_k det(J) (grad r_a . grad r_b) from
  * isoparametric derivatives, bm[E][N^3] = w_i w_j w_k det(J) (may be NULL),
  * xyz[3][E][N^3] node coordinates (may be NULL). */
 int nbx_geom_brick(int ex, int ey, int ez, int N, const double *deform_host,
@@ -102,13 +109,16 @@ int nbx_geom(const double *xyz, int N, int64_t E, double *G, double *bm, void *s
 
 /* Repacks geometric factors given in the layout of the operator's g
  * argument (Section II-B: g(6, N^3, E), the six factors of a node
- * contiguous, g_aos[(e*N^3 + p)*6 + f]) into the [E][6][N^3] layout every
- * other call takes (g_soa[(e*6 + f)*N^3 + p]), f = 0..5 for g1..g6.
- * Device arrays of 6*E*N^3 doubles each, caller-owned; they must not
- * overlap (NBX_EINVAL).  Async on stream, no allocation; E = 0 is a no-op.
- * NBX_EINVAL for N outside [2, 16], E < 0 or a null pointer. */
+ * contiguous, g_aos[(e*N^3 + p)*6 + f]) into the layout every other call
+ * takes, planes of factor pairs (g_soa[((e*3 + f/2)*N^3 + p)*2 + f%2]).
+ * nbx_pair_factors does the same from per-factor planes, [E][6][N^3]
+ * (g6[(e*6 + f)*N^3 + p]).  f = 0..5 for g1..g6.  Device arrays of 6*E*N^3
+ * doubles each, caller-owned; they must not overlap (NBX_EINVAL).  Async
+ * on stream, no allocation; E = 0 is a no-op.  NBX_EINVAL for N outside
+ * [2, 16], E < 0 or a null pointer. */
 int nbx_repack_g_aos_to_soa(const double *g_aos, double *g_soa, int N, int64_t E,
                             void *stream);
+int nbx_pair_factors(const double *g6, double *g_pairs, int N, int64_t E, void *stream);
 
 /* Global node ids of the brick's local nodes (gid_host[E*N^3]) and the
  * homogeneous Dirichlet flags (bnd_host[E*N^3] = 1 on the cube's
@@ -156,7 +166,7 @@ int nbx_pcg_get_tile(int prec, int N);
  * nearest-even, first to FP32, then to gprec = NBX_F16 (IEEE binary16) or
  * NBX_BF16 (bfloat16), stored at G16[((e*3 + f/2)*N^3 + q)*2 + f%2]: three
  * planes per element of 32-bit words holding the factor pairs (g1,g2),
- * (g3,g4), (g5,g6) of a node, low half first.  G (FP64, [E][6][N^3]), G16
+ * (g3,g4), (g5,g6) of a node, low half first.  G (FP64, [E][3][N^3][2]), G16
  * (6*E*N^3 16-bit words, 4-byte aligned) and gscale ([E] float) are device
  * arrays.  Async.
  *

@@ -87,6 +87,7 @@ def lib():
         "nbx_problem_destroy": ([vp], i32),
         "nbx_problem_dinv": ([vp, vp, vp], i32),
         "nbx_repack_g_aos_to_soa": ([vp, vp, i32, i64, vp], i32),
+        "nbx_pair_factors": ([vp, vp, i32, i64, vp], i32),
         "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
         "nbx_pcg_default_opts": ([C.POINTER(PcgOpts)], None),
         "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
@@ -218,12 +219,12 @@ def deriv_device(N: int, device="cuda"):
 
 def geom_brick(ex: int, ey: int, ez: int, N: int, deform=None, with_xyz=False,
                device="cuda", stream=None):
-    """(G [E,6,N^3], bm [E,N^3], xyz [3,E,N^3] or None) for a deformed brick,
-    computed on the device."""
+    """(G [E,3,N^3,2] planes of factor pairs, bm [E,N^3], xyz [3,E,N^3] or
+    None) for a deformed brick, computed on the device."""
     torch = _torch()
     E = ex * ey * ez
     N3 = N ** 3
-    G = torch.empty((E, 6, N3), dtype=torch.float64, device=device)
+    G = torch.empty((E, 3, N3, 2), dtype=torch.float64, device=device)
     bm = torch.empty((E, N3), dtype=torch.float64, device=device)
     xyz = torch.empty((3, E, N3), dtype=torch.float64, device=device) if with_xyz else None
     d = np.ascontiguousarray(deform if deform is not None else
@@ -239,28 +240,39 @@ def geom(xyz, N: int, stream=None):
     if xyz.dim() != 3 or xyz.shape[0] != 3 or xyz.shape[2] != N ** 3:
         raise ValueError("xyz must be [3, E, N^3]")
     E = xyz.shape[1]
-    G = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=xyz.device)
+    G = torch.empty((E, 3, N ** 3, 2), dtype=torch.float64, device=xyz.device)
     bm = torch.empty((E, N ** 3), dtype=torch.float64, device=xyz.device)
     _check(lib().nbx_geom(_dptr(xyz, torch.float64, "xyz"), N, E, _dptr(G), _dptr(bm),
                           _stream(stream)), "nbx_geom")
     return G, bm
 
 
+def _factor_layout(fn: str, src, N: int, out, stream):
+    torch = _torch()
+    n6 = src.numel()
+    if n6 % (6 * N ** 3):
+        raise ValueError("the factors must hold 6 values for every node of whole elements")
+    E = n6 // (6 * N ** 3)
+    out = torch.empty((E, 3, N ** 3, 2), dtype=torch.float64, device=src.device) \
+        if out is None else _need(out, n6, "out")
+    _check(getattr(lib(), fn)(_dptr(src, torch.float64, "factors"),
+                              _dptr(out, torch.float64, "out"), N, E, _stream(stream)), fn)
+    return out
+
+
 def repack_g_aos_to_soa(g_aos, N: int, out=None, stream=None):
     """Geometric factors in the layout of the operator's g argument,
     g(6, N^3, E) with the factor fastest (a float64 tensor of E*N^3*6 values,
-    e.g. shaped [E, N^3, 6]), repacked on the device into [E, 6, N^3]."""
-    torch = _torch()
-    n6 = g_aos.numel()
-    if n6 % (6 * N ** 3):
-        raise ValueError("g_aos must hold 6 factors for every node of whole elements")
-    E = n6 // (6 * N ** 3)
-    out = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=g_aos.device) \
-        if out is None else _need(out, n6, "out")
-    _check(lib().nbx_repack_g_aos_to_soa(_dptr(g_aos, torch.float64, "g_aos"),
-                                         _dptr(out, torch.float64, "out"), N, E,
-                                         _stream(stream)), "nbx_repack_g_aos_to_soa")
-    return out
+    e.g. shaped [E, N^3, 6]), repacked on the device into the library's
+    planes of factor pairs [E, 3, N^3, 2]."""
+    return _factor_layout("nbx_repack_g_aos_to_soa", g_aos, N, out, stream)
+
+
+def pair_factors(g6, N: int, out=None, stream=None):
+    """Geometric factors as one plane per factor, [E, 6, N^3] float64,
+    repacked on the device into the library's planes of factor pairs
+    [E, 3, N^3, 2] (nbx_pair_factors)."""
+    return _factor_layout("nbx_pair_factors", g6, N, out, stream)
 
 
 def brick_ids(ex: int, ey: int, ez: int, N: int):
@@ -273,8 +285,8 @@ def brick_ids(ex: int, ey: int, ez: int, N: int):
 # --------------------------------------------------------------------- AX
 
 def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[int] = None):
-    """w = AX(u) for u [E, N^3] (float64 or float32), G [E, 6, N^3] of the
-    same dtype, D [N, N] float64 (device).  epb forces a tile (elements per
+    """w = AX(u) for u [E, N^3] (float64 or float32), G [E, 3, N^3, 2]
+    (planes of factor pairs) of the same dtype, D [N, N] float64 (device).  epb forces a tile (elements per
     workgroup); by default the library's tile table decides."""
     torch = _torch()
     N = D.shape[0] if N is None else N

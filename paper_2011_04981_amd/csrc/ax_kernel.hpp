@@ -12,8 +12,8 @@
 //   * writes wr, ws to two more LDS slabs for the transposed contractions
 //     and keeps wt in registers.
 // Memory order matters on MI355X's HBM3E: the u column is requested first,
-// then all 6N geometric factors of the column with non-temporal loads (75%
-// of the element's bytes, read exactly once), so that the first slab's
+// then all 6N geometric factors of the column as 3N non-temporal pair loads
+// (75% of the element's bytes, read exactly once), so that the first slab's
 // contractions overlap the factor stream; w is written with non-temporal
 // stores.  Measured on the 32^3 brick at N = 10 this order is worth ~20%
 // over plain loads and stores.  Uniform entries D[k][m] come through the
@@ -66,30 +66,26 @@ __device__ inline T ax_ld_nt(const T *p) { return __builtin_nontemporal_load(p);
 struct g_f16 { uint16_t bits; };
 struct g_bf16 { uint16_t bits; };
 
+// Factor pair q of an element's pair planes (q = h N^3 + node: factors 2h
+// and 2h+1 of the node), streamed once: one non-temporal 16-byte (FP64),
+// 8-byte (FP32) or 4-byte (16-bit storage, widened to FP32) load.
 template <typename T, typename GT>
-__device__ inline T ax_ldg(const GT *p)
+__device__ inline void ax_pair(const GT *Ge, int q, T &lo, T &hi)
 {
-    if constexpr (std::is_same<GT, g_f16>::value) {
-        const uint16_t b = __builtin_nontemporal_load(&p->bits);
-        return (T)(float)__builtin_bit_cast(_Float16, b);
-    } else if constexpr (std::is_same<GT, g_bf16>::value) {
-        const uint16_t b = __builtin_nontemporal_load(&p->bits);
-        return (T)__uint_as_float((uint32_t)b << 16);
+    if constexpr (std::is_same<GT, T>::value) {
+        typedef T pair_t __attribute__((ext_vector_type(2)));
+        const pair_t v = __builtin_nontemporal_load(reinterpret_cast<const pair_t *>(Ge) + q);
+        lo = v.x;
+        hi = v.y;
     } else {
-        return (T)__builtin_nontemporal_load(p);
-    }
-}
-// A 32-bit word of 16-bit storage: the node's factors 2h (low half) and
-// 2h+1 (high half), widened to FP32.
-template <typename GT>
-__device__ inline void ax_half2(uint32_t wd, float &lo, float &hi)
-{
-    if constexpr (std::is_same<GT, g_f16>::value) {
-        lo = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd & 0xffffu));
-        hi = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd >> 16));
-    } else {
-        lo = __uint_as_float(wd << 16);
-        hi = __uint_as_float(wd & 0xffff0000u);
+        const uint32_t wd = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(Ge) + q);
+        if constexpr (std::is_same<GT, g_f16>::value) {
+            lo = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd & 0xffffu));
+            hi = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd >> 16));
+        } else {
+            lo = __uint_as_float(wd << 16);
+            hi = __uint_as_float(wd & 0xffff0000u);
+        }
     }
 }
 
@@ -107,9 +103,10 @@ __device__ inline float ax_fma(float a, float b, float c) { return __builtin_fma
 // blk selects the block's elements [blk*EPB, blk*EPB + EPB) of this
 // operator instance (blockIdx.x for a single operator; a table entry when
 // one launch serves several independent problems).
-// GT is the storage type of G (T, or g_f16 / g_bf16 with T = float); for
-// 16-bit storage G_e holds G_e / gscale[e] (gscale[e] a power of two) in
-// three planes of factor pairs (see ax_half2), and
+// G is in planes of factor pairs (g_index).  GT is its storage type (T,
+// or g_f16 / g_bf16 with T = float); for 16-bit storage G_e holds
+// G_e / gscale[e] (gscale[e] a power of two), each pair in one 32-bit word
+// (see ax_pair), and
 // the element's result is multiplied by gscale[e], which in FP32 is exact
 // and commutes with every rounding of the element's arithmetic.
 template <typename T, int N, int EPB, bool PCG, typename GT = T>
@@ -159,25 +156,17 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
 #pragma unroll
         for (int k = 0; k < N; ++k) uc[k] = uin[base + k * N2 + tc];
     }
-    // 2. ... then every geometric factor of the column, streamed once
+    // 2. ... then every geometric factor of the column, streamed once, a
+    // pair per load (pair planes halve the load count against one plane per
+    // factor: 6.1 -> 6.5 TB/s at N = 10 in FP64)
     constexpr int PF = S::template pf<T>();
-    // factor-major order: consecutive requests cover consecutive addresses,
-    // so a line shared by two 8N^2-byte slabs is asked for twice in a row
+    // plane-major order: consecutive requests cover consecutive addresses,
+    // so a line shared by two slabs is asked for twice in a row
     T g[6][PF];
-    if constexpr (kHalfG) {
-        const uint32_t *Gw = reinterpret_cast<const uint32_t *>(Ge);   // 3 N^3 words
 #pragma unroll
-        for (int h = 0; h < 3; ++h)
+    for (int h = 0; h < 3; ++h)
 #pragma unroll
-            for (int k = 0; k < PF; ++k)
-                ax_half2<GT>(__builtin_nontemporal_load(Gw + h * N3 + k * N2 + tc), g[2 * h][k],
-                             g[2 * h + 1][k]);
-    } else {
-#pragma unroll
-        for (int f = 0; f < 6; ++f)
-#pragma unroll
-            for (int k = 0; k < PF; ++k) g[f][k] = ax_ldg<T>(Ge + f * N3 + k * N2 + tc);
-    }
+        for (int k = 0; k < PF; ++k) ax_pair<T>(Ge, h * N3 + k * N2 + tc, g[2 * h][k], g[2 * h + 1][k]);
     for (int q = t; q < N2; q += NT) s_D[q] = (T)Dg[q];
     if constexpr (PCG) {
         if (valid) {
@@ -220,17 +209,9 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
                 if constexpr ((sizeof(T) == sizeof(double) && N >= 11 && N != 15) ||
                               (sizeof(T) == sizeof(float) && N >= 13))
                     asm volatile("" : "+v"(off) : "v"(wt[k - 1]));
-                if constexpr (kHalfG) {
-                    const uint32_t *gw = reinterpret_cast<const uint32_t *>(Ge) + off;
-                    ax_half2<GT>(__builtin_nontemporal_load(gw), g1, g2);
-                    ax_half2<GT>(__builtin_nontemporal_load(gw + N3), g3, g4);
-                    ax_half2<GT>(__builtin_nontemporal_load(gw + 2 * N3), g5, g6);
-                } else {
-                    const GT *gp = Ge + off;
-                    g1 = ax_ldg<T>(gp); g2 = ax_ldg<T>(gp + N3); g3 = ax_ldg<T>(gp + 2 * N3);
-                    g4 = ax_ldg<T>(gp + 3 * N3); g5 = ax_ldg<T>(gp + 4 * N3);
-                    g6 = ax_ldg<T>(gp + 5 * N3);
-                }
+                ax_pair<T>(Ge, off, g1, g2);
+                ax_pair<T>(Ge, off + N3, g3, g4);
+                ax_pair<T>(Ge, off + 2 * N3, g5, g6);
             }
             const T wr = ax_fma(g3, ut, ax_fma(g2, us, g1 * ur));
             const T ws = ax_fma(g5, ut, ax_fma(g4, us, g2 * ur));

@@ -57,9 +57,8 @@ g16_pack_kernel(int bf16, int N3, const double *__restrict__ G, uint32_t *__rest
     if (threadIdx.x == 0) gscale[e] = ldexpf(1.0f, ex);
     uint32_t *out = G16 + (size_t)e * 3 * N3;
     for (int q = threadIdx.x; q < 3 * N3; q += blockDim.x) {
-        const int h = q / N3, p = q - h * N3;
-        const uint32_t lo = to16(bf16, Ge[(2 * h) * N3 + p] * inv);
-        const uint32_t hi = to16(bf16, Ge[(2 * h + 1) * N3 + p] * inv);
+        const uint32_t lo = to16(bf16, Ge[2 * q] * inv);       // G's pair planes have
+        const uint32_t hi = to16(bf16, Ge[2 * q + 1] * inv);   // the words' order
         out[q] = lo | (hi << 16);
     }
 }

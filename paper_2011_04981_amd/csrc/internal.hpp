@@ -28,6 +28,15 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 constexpr int kMaxN = 16;
 
+// Geometric factors: per element three planes of factor pairs (g1,g2),
+// (g3,g4), (g5,g6), one pair per node, so that the operator fetches a pair
+// with one 16-byte (FP64) or 8-byte (FP32) load.  Factor f of node p of
+// element e:
+__host__ __device__ inline int64_t g_index(int64_t e, int f, int64_t p, int N3)
+{
+    return ((e * 3 + (f >> 1)) * N3 + p) * 2 + (f & 1);
+}
+
 // GLL nodes / weights / derivative matrix computed on the host.
 int gll_host(int N, double *xi, double *w);
 void deriv_host(int N, const double *xi, double *D);

@@ -56,7 +56,7 @@ lp_geom_kernel(int N3, const double *__restrict__ G, float *__restrict__ gfeat)
     double m[6];
     for (int f = 0; f < 6; ++f) {
         double a = 0.0;
-        for (int q = threadIdx.x; q < N3; q += blockDim.x) a += G[((size_t)e * 6 + f) * N3 + q];
+        for (int q = threadIdx.x; q < N3; q += blockDim.x) a += G[g_index(e, f, q, N3)];
         m[f] = lp_block_sum(a, s) / N3;
     }
     const double gd = (m[0] + m[3] + m[5]) / 3.0;

@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 import synthetic as S
+from layout import pairs, planes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -56,7 +57,7 @@ def test_ax_random_factors(N, E):
     u = S.uniform_field(E, N, seed=N)
     G = S.random_factors(E, N, seed=N + 1)
     want = O.ax(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u), cuda(G), nbx.deriv_device(N)))
+    got = host(nbx.ax(cuda(u), cuda(pairs(G)), nbx.deriv_device(N)))
     assert_rel(got, want, TOL)
 
 
@@ -80,7 +81,7 @@ def test_geometry_and_ax_on_deformed_mesh(dims, N):
     b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
     P = O.setup(b)
     G, bm, xyz = nbx.geom_brick(*dims, N, b.deform_array(), with_xyz=True)
-    assert_rel(host(G), P.G, TOL)
+    assert_rel(planes(host(G), N ** 3), P.G, TOL)
     assert_rel(host(bm), P.bm, TOL)
     assert_rel(host(xyz)[0], P.x, 1e-15)
     u = S.uniform_field(b.E, N, seed=3)
@@ -95,7 +96,7 @@ def test_ax_full_size_seeded_factors():
     print("ax parity at E=32768 N=10 (seeded factors)", flush=True)
     u = S.uniform_field(E, N, seed=0)
     G = S.random_factors(E, N, seed=1)
-    w = nbx.ax(cuda(u), cuda(G), nbx.deriv_device(N))
+    w = nbx.ax(cuda(u), cuda(pairs(G)), nbx.deriv_device(N))
     assert_rel(host(w), O.ax(u, G, O.deriv(N)), TOL)
 
 
@@ -114,7 +115,7 @@ def test_ax_full_size_deformed_c2():
     x, y, z = O.brick_coords(b, xi)
     Go, bmo, _ = O.geom(N, D, wq, x, y, z)
     del x, y, z
-    assert_rel(host(G), Go, TOL)
+    assert_rel(planes(host(G), N ** 3), Go, TOL)
     assert_rel(host(bm), bmo, TOL)
     u = S.uniform_field(b.E, N, seed=0)
     w = nbx.ax(cuda(u), G, nbx.deriv_device(N))
@@ -123,7 +124,7 @@ def test_ax_full_size_deformed_c2():
 
 def test_ax_is_deterministic():
     N, E = 10, 300
-    u = cuda(S.uniform_field(E, N, 5)); G = cuda(S.random_factors(E, N, 6))
+    u = cuda(S.uniform_field(E, N, 5)); G = cuda(pairs(S.random_factors(E, N, 6)))
     D = nbx.deriv_device(N)
     a = host(nbx.ax(u, G, D)); b = host(nbx.ax(u, G, D))
     assert np.array_equal(a, b)
@@ -137,7 +138,8 @@ def test_ax_fp32_error_vs_oracle(N):
     u = S.uniform_field(E, N, seed=11)
     G = S.random_factors(E, N, seed=12)
     want = O.ax(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(pairs(G), torch.float32),
+                      nbx.deriv_device(N)))
     err = rel(got, want)
     print(f"fp32 AX N={N}: normwise error {err:.3e}")
     assert err <= 300 * np.finfo(np.float32).eps
@@ -296,7 +298,8 @@ def test_pcg_one_step_full_size_c2():
 def test_every_tile_is_bit_identical(N, E):
     """The autotuner's search space: every elements-per-workgroup choice
     that fits computes the same bits (including the ragged last block)."""
-    u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(S.random_factors(E, N, seed=32))
+    G6 = S.random_factors(E, N, seed=32)
+    u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(pairs(G6))
     D = nbx.deriv_device(N)
     ref = None
     for epb in (1, 2, 4):
@@ -307,7 +310,7 @@ def test_every_tile_is_bit_identical(N, E):
             continue
         if ref is None:
             ref = w
-            assert_rel(w, O.ax(host(u), host(G), O.deriv(N)), TOL)
+            assert_rel(w, O.ax(host(u), G6, O.deriv(N)), TOL)
         else:
             assert np.array_equal(w, ref), epb
 
@@ -329,7 +332,8 @@ def test_ax_fp32_matches_oracle_fp32(N):
     u = S.uniform_field(E, N, seed=41).astype(np.float32)
     G = S.random_factors(E, N, seed=42).astype(np.float32)
     want = O.ax_f32(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(pairs(G), torch.float32),
+                      nbx.deriv_device(N)))
     assert_rel(got, want, 16 * N * np.finfo(np.float32).eps)
 
 
@@ -493,18 +497,25 @@ def test_indefinite_operator_reports_breakdown(prec):
 
 
 @pytest.mark.parametrize("N,E", [(2, 1), (3, 7), (10, 33), (16, 3)])
-def test_repack_paper_factor_layout(N, E):
-    """nbx_repack_g_aos_to_soa: factors in the layout of the operator's g
-    argument, g(6, N^3, E) with the factor fastest, into [E][6][N^3] bit for
-    bit (node counts below, at and off the kernel's 256-node blocks)."""
-    G = cuda(S.random_factors(E, N, seed=41))            # [E, 6, N^3]
-    aos = G.permute(0, 2, 1).contiguous()                # [E, N^3, 6]
-    soa = nbx.repack_g_aos_to_soa(aos, N)
-    assert torch.equal(soa, G)
-    out = torch.full_like(G, float("nan"))
+def test_factor_layout_conversions(N, E):
+    """nbx_repack_g_aos_to_soa (from the layout of the operator's g
+    argument, g(6, N^3, E) with the factor fastest) and nbx_pair_factors
+    (from one plane per factor) into the library's planes of factor pairs,
+    bit for bit (node counts below, at and off the kernels' 256-node
+    blocks); AX agrees on the converted factors."""
+    G6 = S.random_factors(E, N, seed=41)                 # [E, 6, N^3]
+    want = cuda(pairs(G6))                               # [E, 3, N^3, 2]
+    aos = cuda(G6.transpose(0, 2, 1))                    # [E, N^3, 6]
+    assert torch.equal(nbx.repack_g_aos_to_soa(aos, N), want)
+    assert torch.equal(nbx.pair_factors(cuda(G6), N), want)
+    out = torch.full_like(want, float("nan"))
     nbx.repack_g_aos_to_soa(aos, N, out=out)
-    assert torch.equal(out, G)
+    assert torch.equal(out, want)
     with pytest.raises(nbx.NbxError):                    # overlapping arrays
         nbx.repack_g_aos_to_soa(aos, N, out=aos)
+    with pytest.raises(nbx.NbxError):
+        nbx.pair_factors(want, N, out=want)
     empty = torch.empty((0, N ** 3, 6), dtype=torch.float64, device=DEV)
-    assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 6, N ** 3)
+    assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 3, N ** 3, 2)
+    u = S.uniform_field(E, N, seed=42)
+    assert_rel(host(nbx.ax(cuda(u), want, nbx.deriv_device(N))), O.ax(u, G6, O.deriv(N)), TOL)
