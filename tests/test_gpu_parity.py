@@ -519,3 +519,24 @@ def test_factor_layout_conversions(N, E):
     assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 3, N ** 3, 2)
     u = S.uniform_field(E, N, seed=42)
     assert_rel(host(nbx.ax(cuda(u), want, nbx.deriv_device(N))), O.ax(u, G6, O.deriv(N)), TOL)
+
+
+@pytest.mark.parametrize("N", [11, 13, 16])
+def test_pcg_large_elements(N):
+    """Element orders whose fused first stage loads part of the factor
+    column inside the slab loop (FP64 from N = 11, FP32 from N = 13): FP64
+    PCG and the FP32 / FP16-G mixed solves against the oracle's solution."""
+    b = S.Brick(2, 2, 1, N, ((0.05, 2, 2, 2),) * 3)
+    print(f"large-element solves N={N}", flush=True)
+    P = O.setup(b)
+    ora = O.pcg(P, max_iter=5000, rtol=1e-10)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, check_every=7)
+    assert r.status == 0 and abs(r.iters - ora.iters) <= 1
+    assert rel(host(x), ora.x) <= 1e-8
+    for prec in (nbx.F32, nbx.F16):
+        xm, rm = st.problem.pcg(st.b, rtol=1e-10, max_iter=8000, check_every=7, prec=prec)
+        print(f"  prec {prec}: {rm.iters} it, {rm.outer_iters} updates, "
+              f"true relres {rm.true_relres:.2e}")
+        assert rm.status == 0 and rm.true_relres <= 2e-10
+        assert rel(host(xm), ora.x) <= 1e-7
