@@ -136,15 +136,16 @@ int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host, uint8_t *bnd
 int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
            void *w, void *stream);
 
-/* nbx_ax with an explicit tile: epb elements per workgroup (1, 2 or 4).
+/* nbx_ax with an explicit tile: epb elements per workgroup (1, 2, 4 or 8).
  * Every tile computes bit-identical results; tiles differ only in speed.
  * NBX_EINVAL for another epb, NBX_EUNSUPPORTED if the tile's LDS would
- * exceed 160 KB. */
+ * exceed 160 KB or its workgroup 1024 threads. */
 int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
                  void *w, int epb, void *stream);
 
 /* The tile nbx_ax uses for (prec, N) (process-wide; set by the
- * autotuner).  get returns epb or a negative status.  prec NBX_F64 or
+ * autotuner).  get returns epb or a negative status; set refuses a tile
+ * that does not fit (NBX_EUNSUPPORTED, as nbx_ax_tiled).  prec NBX_F64 or
  * NBX_F32 (the FP32 table also serves nbx_ax_g16). */
 int nbx_ax_set_tile(int prec, int N, int epb);
 int nbx_ax_get_tile(int prec, int N);

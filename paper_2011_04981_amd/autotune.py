@@ -26,7 +26,7 @@ from . import F32, F64, NbxError, ax, get_pcg_tile, lib, set_pcg_tile, set_tile
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tiles.json")
 PREC_NAME = {F64: "f64", F32: "f32"}
-TILES = (1, 2, 4)
+TILES = (1, 2, 4, 8)
 
 
 def cache_path() -> str:

@@ -54,7 +54,15 @@ void init_tiles()
 
 int prec_slot(int prec) { return prec == NBX_F64 ? 0 : 1; }   // FP32 arithmetic: one table
 
-bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4; }
+bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4 || epb == 8; }
+
+// The host side of AxShape::fits: LDS and thread count of a tile.
+bool tile_fits(int prec, int N, int epb)
+{
+    const int64_t N2 = N * N, N3 = N2 * N, nt = (epb * N2 + 63) / 64 * 64;
+    const int64_t word = prec == NBX_F64 ? 8 : 4;
+    return nt <= 1024 && (3 * epb * N3 + N2) * word + (nt / 64) * 8 <= 160 * 1024;
+}
 
 }  // namespace
 
@@ -159,6 +167,7 @@ extern "C" int nbx_ax_tiled(int prec, const void *u, const void *G, const double
 static int set_tile(int kind, int prec, int N, int epb)
 {
     if (N < 2 || N > kMaxN || !valid_epb(epb)) return NBX_EINVAL;
+    if (!tile_fits(prec, N, epb)) return NBX_EUNSUPPORTED;
     if (prec != NBX_F64 && prec != NBX_F32) return NBX_EUNSUPPORTED;
     init_tiles();
     g_tile[kind][prec_slot(prec)][N].store(epb);

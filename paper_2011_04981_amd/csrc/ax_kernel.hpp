@@ -43,11 +43,13 @@ struct AxShape {
         return sizeof(T) == sizeof(double) ? (N <= 10 ? N : (N <= 12 ? 6 : 4))
                                            : (N <= 12 ? N : 8);
     }
-    // LDS of one block: three element slabs per element, D, reduction slots.
+    // LDS of one block (three element slabs per element, D, reduction
+    // slots) within the CU's 160 KB, and at most 1024 threads.
     template <typename T>
     static constexpr bool fits()
     {
-        return (3 * EPB * N3 + N2) * sizeof(T) + (NT / 64) * sizeof(double) <= 160 * 1024;
+        return NT <= 1024 &&
+               (3 * EPB * N3 + N2) * sizeof(T) + (NT / 64) * sizeof(double) <= 160 * 1024;
     }
 };
 
@@ -268,7 +270,7 @@ ax_kernel(const T *__restrict__ uin, const GT *__restrict__ G, const double *__r
 }
 
 // Elements per workgroup the library may use (the autotuner's search space).
-constexpr int kEpbChoices[] = {1, 2, 4};
+constexpr int kEpbChoices[] = {1, 2, 4, 8};
 
 template <typename T, bool PCG, int N, typename GT = T>
 int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p, double *part,
@@ -290,6 +292,7 @@ int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p,
         NBX_EPB_CASE(1)
         NBX_EPB_CASE(2)
         NBX_EPB_CASE(4)
+        NBX_EPB_CASE(8)
         default: return NBX_EINVAL;
     }
 #undef NBX_EPB_CASE

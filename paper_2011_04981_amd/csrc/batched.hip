@@ -126,7 +126,7 @@ int launch_b_ax(int epb, const BDesc *desc, const BEntry *tab, int nblk, hipStre
         } else {                                                                             \
             return NBX_EUNSUPPORTED;                                                         \
         }
-        NBX_BAX(1) NBX_BAX(2) NBX_BAX(4)
+        NBX_BAX(1) NBX_BAX(2) NBX_BAX(4) NBX_BAX(8)
 #undef NBX_BAX
         default: return NBX_EINVAL;
     }

@@ -33,7 +33,17 @@ def test_tile_table_rejects_invalid_entries():
         nbx.set_tile(nbx.F64, 17, 2)
     with pytest.raises(nbx.NbxError):
         nbx.set_tile(nbx.BF16, 10, 2)
-    assert nbx.get_tile(nbx.F64, 10) in (1, 2, 4)
+    # tiles that do not fit: 8 FP64 elements of 10^3 nodes need 192 KB of
+    # LDS; 8 elements of 12^2 columns need 1152 threads
+    for p, N in ((nbx.F64, 10), (nbx.F32, 12)):
+        with pytest.raises(nbx.NbxError) as e:
+            nbx.set_tile(p, N, 8)
+        assert e.value.status == -2
+    old = nbx.get_tile(nbx.F32, 10)
+    nbx.set_tile(nbx.F32, 10, 8)                    # 96 KB, 832 threads: fits
+    assert nbx.get_tile(nbx.F32, 10) == 8
+    nbx.set_tile(nbx.F32, 10, old)
+    assert nbx.get_tile(nbx.F64, 10) in (1, 2, 4, 8)
 
 
 def test_fused_stage_table_is_separate(tmp_path):

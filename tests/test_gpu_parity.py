@@ -302,7 +302,7 @@ def test_every_tile_is_bit_identical(N, E):
     u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(pairs(G6))
     D = nbx.deriv_device(N)
     ref = None
-    for epb in (1, 2, 4):
+    for epb in (1, 2, 4, 8):
         try:
             w = host(nbx.ax(u, G, D, epb=epb))
         except nbx.NbxError as e:
