@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--learned-train", type=int, default=8,
                     help="training meshes (32x16x16, N=10) for the learned leg")
     ap.add_argument("--learned-epochs", type=int, default=10)
+    ap.add_argument("--dssum-only", type=int, default=0, metavar="K",
+                    help="profiling mode: K dssum passes (FP64, then FP32) on the brick's "
+                         "plan and random vectors, then exit")
     return ap.parse_args()
 
 
@@ -99,7 +102,7 @@ def traffic_record(kernel_hash):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "nbx runs on one GPU per process; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
 
@@ -116,6 +119,19 @@ def main():
     flops = nbx.ax_flops(N, E)
     abytes = nbx.ax_bytes(N, E)
     out = {}
+
+    if a.dssum_only:
+        # the exchange alone, for kernel traces and counters
+        gid, bnd = nbx.brick_ids(brick.ex, brick.ey, brick.ez, N)
+        gs = nbx.GS(gid, bnd)
+        g = torch.Generator(device=dev).manual_seed(0)
+        for dt in (torch.float64, torch.float32):
+            v = torch.rand(gid.size, dtype=dt, device=dev, generator=g)
+            for _ in range(a.dssum_only):
+                gs.dssum(v)
+            torch.cuda.synchronize()
+            log(f"dssum {dt}: {a.dssum_only} passes over {gid.size} local nodes")
+        return
 
     with torch.cuda.stream(stream):
         log(f"set-up: E={E} N={N}")
