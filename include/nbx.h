@@ -145,8 +145,9 @@ int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N,
 
 /* The tile nbx_ax uses for (prec, N) (process-wide; set by the
  * autotuner).  get returns epb or a negative status; set refuses a tile
- * that does not fit (NBX_EUNSUPPORTED, as nbx_ax_tiled).  prec NBX_F64 or
- * NBX_F32 (the FP32 table also serves nbx_ax_g16). */
+ * that does not fit (NBX_EUNSUPPORTED, as nbx_ax_tiled).  prec NBX_F64,
+ * NBX_F32, or NBX_F16 / NBX_BF16 for the one table of the 16-bit-G kernels
+ * (nbx_ax_g16 and the inner iterations of NBX_F16 / NBX_BF16 solves). */
 int nbx_ax_set_tile(int prec, int N, int epb);
 int nbx_ax_get_tile(int prec, int N);
 /* The tile of the solvers' fused first stage (p = z + beta p, w = AX(p),

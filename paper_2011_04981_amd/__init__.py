@@ -125,7 +125,7 @@ def _apply_tile_cache(L) -> None:
         rec = json.load(f)
     for pname, rows in rec.get("tiles", {}).items():
         kind, _, pn = pname.rpartition("_")
-        prec = {"f64": F64, "f32": F32}.get(pn)
+        prec = {"f64": F64, "f32": F32, "g16": F16}.get(pn)
         setter = {"": L.nbx_ax_set_tile, "pcg": L.nbx_pcg_set_tile}.get(kind)
         if prec is None or setter is None:
             continue

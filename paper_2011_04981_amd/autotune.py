@@ -21,11 +21,14 @@ import os
 import statistics
 from typing import Dict, Iterable, Optional
 
-from . import F32, F64, NbxError, ax, get_pcg_tile, lib, set_pcg_tile, set_tile
+from . import (F16, F32, F64, NbxError, ax, ax_g16, g16_pack, get_pcg_tile, get_tile, lib,
+               set_pcg_tile, set_tile)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tiles.json")
-PREC_NAME = {F64: "f64", F32: "f32"}
+# the 16-bit-G kernels (FP16 and BF16 storage, FP32 arithmetic) share one
+# table, timed with FP16 storage
+PREC_NAME = {F64: "f64", F32: "f32", F16: "g16"}
 TILES = (1, 2, 4, 8)
 
 
@@ -42,30 +45,44 @@ def time_tiles(prec: int, N: int, nodes: int = 16_000_000, reps: int = 20,
     E = max(64, nodes // N ** 3)
     g = torch.Generator(device="cuda").manual_seed(seed)
     u = torch.rand((E, N ** 3), dtype=dtype, device="cuda", generator=g)
-    G = torch.rand((E, 3, N ** 3, 2), dtype=dtype, device="cuda", generator=g)
+    G = torch.rand((E, 3, N ** 3, 2), dtype=torch.float64 if prec == F16 else dtype,
+                   device="cuda", generator=g)
     w = torch.empty_like(u)
     from . import deriv_device
     D = deriv_device(N)
+    if prec == F16:
+        G16, gsc = g16_pack(G, N, F16)
+        old = get_tile(F16, N)
+
+    def run(epb):
+        if prec == F16:
+            set_tile(F16, N, epb)         # nbx_ax_g16 takes its tile from the table
+            ax_g16(u, G16, gsc, D, F16, out=w)
+        else:
+            ax(u, G, D, out=w, epb=epb)
+
     out = {}
     for epb in TILES:
         try:
-            ax(u, G, D, out=w, epb=epb)
+            run(epb)
         except NbxError as e:
             if e.status == -2:
                 continue
             raise
         for _ in range(warmup):
-            ax(u, G, D, out=w, epb=epb)
+            run(epb)
         times = []
         for _ in range(reps):
             s = torch.cuda.Event(enable_timing=True)
             t = torch.cuda.Event(enable_timing=True)
             s.record()
-            ax(u, G, D, out=w, epb=epb)
+            run(epb)
             t.record()
             t.synchronize()
             times.append(s.elapsed_time(t) * 1e-3)
         out[epb] = statistics.median(times)
+    if prec == F16:
+        set_tile(F16, N, old)
     return out
 
 
@@ -96,7 +113,7 @@ def time_pcg_tiles(prec: int, N: int, nodes: int = 8_000_000, iters: int = 60,
                 if prec == F64:
                     _, r = st.problem.pcg(st.b, max_iter=iters, fixed_iters=1, check_every=20)
                 else:
-                    _, r = st.problem.pcg(st.b, rtol=1e-6, max_iter=20 * iters, prec=F32,
+                    _, r = st.problem.pcg(st.b, rtol=1e-6, max_iter=20 * iters, prec=prec,
                                           check_every=20)
             except NbxError as e:
                 if e.status == -2:
@@ -112,7 +129,7 @@ def time_pcg_tiles(prec: int, N: int, nodes: int = 8_000_000, iters: int = 60,
     return out
 
 
-def tune(Ns: Iterable[int] = (6, 8, 10, 12), precs: Iterable[int] = (F64, F32),
+def tune(Ns: Iterable[int] = (6, 8, 10, 12), precs: Iterable[int] = (F64, F32, F16),
          nodes: int = 16_000_000, reps: int = 20, apply: bool = True,
          pcg: bool = True) -> dict:
     """Times every tile for every (precision, N), installs the fastest and

@@ -32,19 +32,20 @@ int ax_pcg_launch_g_bf16(int N, int epb, const void *G, const float *gscale, con
 
 namespace {
 
-// Elements per workgroup by [kind][precision][N]; kind 0 is the plain
+// Elements per workgroup by [kind][operator][N]; kind 0 is the plain
 // operator (nbx_ax), kind 1 the solvers' fused first stage (p update, AX,
-// <p,w> partials), whose register and LDS use differ.  Defaults: two
-// elements per block where a block's three LDS slabs stay small (measured
-// best at N = 10 in FP64), one for the large elements.
-std::atomic<int> g_tile[2][2][kMaxN + 1];
+// <p,w> partials), whose register and LDS use differ; operator 0 FP64, 1
+// FP32, 2 FP32 arithmetic on 16-bit G (FP16 and BF16 storage share it).
+// Defaults: two elements per block where a block's three LDS slabs stay
+// small (measured best at N = 10 in FP64), one for the large elements.
+std::atomic<int> g_tile[2][3][kMaxN + 1];
 std::atomic<bool> g_tile_init{false};
 
 void init_tiles()
 {
     if (g_tile_init.load()) return;
     for (int k = 0; k < 2; ++k)
-        for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 3; ++p)
             for (int n = 0; n <= kMaxN; ++n) {
                 int e = n <= 6 ? 4 : (n <= 12 ? 2 : 1);
                 g_tile[k][p][n].store(e);
@@ -52,7 +53,7 @@ void init_tiles()
     g_tile_init.store(true);
 }
 
-int prec_slot(int prec) { return prec == NBX_F64 ? 0 : 1; }   // FP32 arithmetic: one table
+int prec_slot(int prec) { return prec == NBX_F64 ? 0 : (prec == NBX_F32 ? 1 : 2); }
 
 bool valid_epb(int epb) { return epb == 1 || epb == 2 || epb == 4 || epb == 8; }
 
@@ -111,7 +112,7 @@ int ax_pcg_launch_f32(const float *G, const double *D, int N, int64_t E, const f
 int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscale,
                   const double *D, int N, int64_t E, float *w, hipStream_t s)
 {
-    const int epb = ax_tile(NBX_F32, N);
+    const int epb = ax_tile(NBX_F16, N);
     return gprec == NBX_F16 ? ax_launch_g_f16(N, epb, u, G16, gscale, D, w, E, s)
                             : ax_launch_g_bf16(N, epb, u, G16, gscale, D, w, E, s);
 }
@@ -120,7 +121,7 @@ int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const dou
                       int64_t E, const float *z, float *p, float *w, double *part,
                       const double *scal, hipStream_t s)
 {
-    const int epb = pcg_tile(NBX_F32, N);
+    const int epb = pcg_tile(NBX_F16, N);
     return gprec == NBX_F16
                ? ax_pcg_launch_g_f16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s)
                : ax_pcg_launch_g_bf16(N, epb, G16, gscale, D, E, z, p, w, part, scal, s);
@@ -167,8 +168,9 @@ extern "C" int nbx_ax_tiled(int prec, const void *u, const void *G, const double
 static int set_tile(int kind, int prec, int N, int epb)
 {
     if (N < 2 || N > kMaxN || !valid_epb(epb)) return NBX_EINVAL;
+    if (prec != NBX_F64 && prec != NBX_F32 && prec != NBX_F16 && prec != NBX_BF16)
+        return NBX_EUNSUPPORTED;
     if (!tile_fits(prec, N, epb)) return NBX_EUNSUPPORTED;
-    if (prec != NBX_F64 && prec != NBX_F32) return NBX_EUNSUPPORTED;
     init_tiles();
     g_tile[kind][prec_slot(prec)][N].store(epb);
     return NBX_OK;
@@ -177,7 +179,8 @@ static int set_tile(int kind, int prec, int N, int epb)
 static int get_tile(int kind, int prec, int N)
 {
     if (N < 2 || N > kMaxN) return NBX_EINVAL;
-    if (prec != NBX_F64 && prec != NBX_F32) return NBX_EUNSUPPORTED;
+    if (prec != NBX_F64 && prec != NBX_F32 && prec != NBX_F16 && prec != NBX_BF16)
+        return NBX_EUNSUPPORTED;
     return kind == 0 ? ax_tile(prec, N) : pcg_tile(prec, N);
 }
 

@@ -17,8 +17,10 @@
 // contractions overlap the factor stream; w is written with non-temporal
 // stores.  Measured on the 32^3 brick at N = 10 this order is worth ~20%
 // over plain loads and stores.  Uniform entries D[k][m] come through the
-// scalar cache (FP64) or as LDS broadcasts (FP32); per-lane rows and
-// columns of D sit in registers.
+// scalar cache (converted to FP32 by the VALU in the FP32 kernels, which
+// are bound by LDS traffic: taking them from LDS as broadcasts made the
+// FP16-G fused stage 7 % slower); per-lane rows and columns of D sit in
+// registers.
 #pragma once
 
 #include "internal.hpp"
@@ -121,7 +123,6 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
 #pragma clang fp contract(off)
     using S = AxShape<N, EPB>;
     constexpr int N2 = S::N2, N3 = S::N3, NT = S::NT, NACT = S::NACT;
-    constexpr bool kDLds = sizeof(T) != sizeof(double);   // uniform D from LDS
     __shared__ T s_u[EPB * N3];
     __shared__ T s_wr[EPB * N3];
     __shared__ T s_ws[EPB * N3];
@@ -197,7 +198,7 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
             for (int m = 0; m < N; ++m) us = ax_fma(Dj[m], su[k * N2 + m * N + i], us);
 #pragma unroll
             for (int m = 0; m < N; ++m)
-                ut = ax_fma(kDLds ? s_D[k * N + m] : (T)Dg[k * N + m], uc[m], ut);
+                ut = ax_fma((T)Dg[k * N + m], uc[m], ut);
             T g1, g2, g3, g4, g5, g6;
             if (k < PF) {
                 g1 = g[0][k]; g2 = g[1][k]; g3 = g[2][k]; g4 = g[3][k]; g5 = g[4][k]; g6 = g[5][k];
@@ -240,7 +241,7 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
             for (int m = 0; m < N; ++m) acc = ax_fma(DTj[m], sws[k * N2 + m * N + i], acc);
 #pragma unroll
             for (int m = 0; m < N; ++m)
-                acc = ax_fma(kDLds ? s_D[m * N + k] : (T)Dg[m * N + k], wt[m], acc);
+                acc = ax_fma((T)Dg[m * N + k], wt[m], acc);
             if constexpr (kHalfG) acc *= gsc;
             if (valid) ax_st_nt(acc, w + base + k * N2 + tc);
             if constexpr (PCG) pw += (double)uc[k] * (double)acc;

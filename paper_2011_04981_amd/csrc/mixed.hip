@@ -54,7 +54,7 @@ unsigned grid_for(int64_t n)
 int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
 {
     const GsPlan &gs = P->gs->plan;
-    const int nb1 = ax_blocks(NBX_F32, P->N, P->E);
+    const int nb1 = ax_blocks(P->inner_fmt, P->N, P->E);   // the inner operator's tile
     const int nb3 = sk::red_blocks(P->n, sk::Vec<float>::W);
     for (int it = 0; it < n_iter; ++it) {
         int st = P->inner_fmt == NBX_F32
@@ -140,7 +140,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
     NBX_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 10;
     if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
-                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(NBX_F32, P->N))) {
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(P->inner_fmt, P->N))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -154,7 +154,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
-        P->g32_tile = pcg_tile(NBX_F32, P->N);
+        P->g32_tile = pcg_tile(P->inner_fmt, P->N);
     }
     int done = 0;
     while (true) {
@@ -289,7 +289,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
     const double delta = (o.inner_rtol > 0 && o.inner_rtol < 1) ? o.inner_rtol : 0.1;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
     if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
-                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(NBX_F32, P->N))) {
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(P->inner_fmt, P->N))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -303,7 +303,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
-        P->g32_tile = pcg_tile(NBX_F32, P->N);
+        P->g32_tile = pcg_tile(P->inner_fmt, P->N);
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
