@@ -540,3 +540,27 @@ def test_pcg_large_elements(N):
               f"true relres {rm.true_relres:.2e}")
         assert rm.status == 0 and rm.true_relres <= 2e-10
         assert rel(host(xm), ora.x) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_mixed_solve_with_interior_shared_node(prec):
+    """Mixed solves on a plan that identifies two element-interior nodes
+    (an unusual but valid SPD assembly: the exchange then also joins
+    interior copies) agree with the FP64 solve."""
+    ex, N = 2, 5
+    gid, bnd = nbx.brick_ids(ex, 1, 1, N)
+    N3 = N ** 3
+    interior = (2 * N + 2) * N + 2                 # node (2, 2, 2) of each element
+    gid = gid.copy()
+    gid[N3 + interior] = gid[interior]
+    gs = nbx.GS(gid, bnd)
+    D = nbx.deriv_device(N)
+    G, _, _ = nbx.geom_brick(ex, 1, 1, N)
+    P = nbx.Problem(G, D, N, gs)
+    b = torch.ones((ex, N3), dtype=torch.float64, device=DEV)
+    gs.dssum(b)
+    x64, r64 = P.pcg(b, rtol=1e-10, max_iter=500)
+    x, r = P.pcg(b, rtol=1e-10, max_iter=2000, prec={"f32": nbx.F32, "f16": nbx.F16}[prec])
+    print(f"{prec}: {r.iters} it, true relres {r.true_relres:.2e} (FP64 {r64.iters} it)")
+    assert r64.status == 0 and r.status == 0 and r.true_relres <= 2e-10
+    assert rel(host(x), host(x64)) <= 1e-8
