@@ -512,6 +512,35 @@ def main():
                                       for N in (6, 8, 10, 12)}}
             log(f"batched: {wall:.3f} s vs sequential {seq:.3f} s, "
                 f"p50 {pct(0.5):.4f} s p99 {pct(0.99):.4f} s")
+            # the same batch with FP16-stored G in the inner iterations
+            # (reliable updates; per-solve latency from the host)
+            kw16 = dict(rtol=1e-10, max_iter=10000, check_every=20, prec=nbx.F16,
+                        inner_rtol=0.1)
+            try:
+                nbx.pcg_batched(probs, bs, **kw16)
+                h0 = time.perf_counter()
+                xm, resm, latm = nbx.pcg_batched(probs, bs, **kw16)
+                wallm = time.perf_counter() - h0
+                errm = max(float((a_ - b_).abs().max() / b_.abs().max())
+                           for a_, b_ in zip(xm, xs))
+                latm_sorted = sorted(latm)
+                pctm = lambda q: latm_sorted[min(len(latm_sorted) - 1,
+                                                 int(q * len(latm_sorted)))]
+                out["batched"]["mixed_f16_storage"] = {
+                    "wall_seconds": round(wallm, 4),
+                    "speedup_vs_fp64_batch": round(wall / wallm, 3),
+                    "converged": int(sum(r.flag == 1 for r in resm)),
+                    "max_true_relres": max(r.true_relres for r in resm),
+                    "fell_back": int(sum(r.fell_back for r in resm)),
+                    "max_err_vs_fp64_batch": errm,
+                    "latency_p50_s": round(pctm(0.50), 5),
+                    "latency_p99_s": round(pctm(0.99), 5)}
+                log(f"batched FP16-G mixed: {wallm:.3f} s, p50 {pctm(0.5):.4f} s, "
+                    f"p99 {pctm(0.99):.4f} s, max true relres "
+                    f"{max(r.true_relres for r in resm):.2e}")
+                del xm
+            except nbx.NbxError as e:
+                out["batched"]["mixed_f16_storage"] = {"unavailable": str(e)}
             del sets, probs, bs, xs
             torch.cuda.empty_cache()
 

@@ -307,10 +307,15 @@ int nbx_pcg(nbx_problem *p, const double *b, double *x, const nbx_pcg_opts *opts
  * kernels, Section IV).  probs, b and x are host arrays of nprob handles /
  * device pointers; results[nprob] is filled per problem (seconds = the whole
  * batch); solve_seconds[nprob] (may be NULL) receives each problem's time
- * from the batch start to its convergence on the device clock.  Results are
- * bit-identical to nbx_pcg on each problem alone.  Synchronous.  Only
- * opts->prec == NBX_F64.  Returns NBX_OK if every problem converged, else
- * NBX_NOT_CONVERGED or NBX_EBREAKDOWN.  A problem must not appear twice. */
+ * from the batch start to its convergence on the device clock.  With
+ * opts->prec NBX_F32, NBX_F16 or NBX_BF16 (mixed_mode 0, reliable updates;
+ * mixed_mode 1 gives NBX_EUNSUPPORTED) the FP32 iterations of all problems
+ * run together the same way and each problem's FP64 residual replacement
+ * follows between replays; solve_seconds is then taken on the host when a
+ * problem's last step ends.  Results are bit-identical to nbx_pcg with the
+ * same options on each problem alone.  Synchronous.  Returns NBX_OK if
+ * every problem converged, else NBX_NOT_CONVERGED or NBX_EBREAKDOWN.  A
+ * problem must not appear twice. */
 int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b, double *const *x,
                     int nprob, const nbx_pcg_opts *opts, nbx_pcg_result *results,
                     double *solve_seconds, void *stream);

@@ -278,15 +278,127 @@ reliable_reduce_kernel(int nb, const double *__restrict__ part, double *__restri
 
 }  // namespace
 
+int reliable_start(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                   hipStream_t s)
+{
+    const GsPlan &gs = P->gs->plan;
+    const int nb = sk::red_blocks(P->n);
+    const double delta = (o.inner_rtol > 0 && o.inner_rtol < 1) ? o.inner_rtol : 0.1;
+    // x = 0; r64 = b; <b,b>_c; FP32 state from b
+    NBX_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)P->n, s));
+    hipLaunchKernelGGL(sk::resid_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, b, x,
+                       gs.info, P->r, P->part3);
+    hipLaunchKernelGGL(sk::sum2_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3, P->tmp2);
+    hipLaunchKernelGGL((sk::init_kernel<float, double>), dim3(nb), dim3(sk::kRedThreads), 0, s,
+                       P->n, P->r, P->dinv32, gs.info, P->d32, P->r32, P->z32, P->p32, P->part3);
+    hipLaunchKernelGGL(sk::init_reduce_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3,
+                       P->scal32, delta, 0, o.max_iter);
+    hipLaunchKernelGGL(mixed_setup_kernel, dim3(1), dim3(1), 0, s, P->scal32, P->tmp2, o.rtol,
+                       delta);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+int reliable_step(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                  const double *h, ReliableState &rs, hipStream_t s)
+{
+    if (h[kSlotFinal] == 1.0) { rs.done = 1; return NBX_OK; }     // zero right-hand side
+    if (h[NBX_S_FLAG] == 2.0) { rs.fell_back = rs.done = 1; return NBX_OK; }
+    const GsPlan &gs = P->gs->plan;
+    const int nb = sk::red_blocks(P->n);
+    // reliable update (also after the iteration limit, to report x)
+    hipLaunchKernelGGL(fold_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n, P->d32, x);
+    NBX_LAUNCH_CHECK();
+    int st = ax_launch_f64(x, P->G, P->D, P->N, P->E, P->w, s);
+    if (st != NBX_OK) return st;
+    st = dssum_launch<double>(gs, P->w, 1, s);
+    if (st != NBX_OK) return st;
+    const bool at_limit = h[NBX_S_FLAG] == sk::kFlagLimit;
+    hipLaunchKernelGGL(replace_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, b, P->w,
+                       P->dinv32, gs.info, P->r32, P->z32, P->part3);
+    hipLaunchKernelGGL(reliable_reduce_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3,
+                       P->scal32);
+    NBX_LAUNCH_CHECK();
+    double *g = P->h_scal;
+    NBX_HIP(hipMemcpyAsync(g, P->scal32, sizeof(double) * NBX_SCAL_LEN, hipMemcpyDeviceToHost,
+                           s));
+    NBX_HIP(hipStreamSynchronize(s));
+    ++rs.updates;
+    if (g[kSlotFinal] == 1.0 || at_limit || g[NBX_S_FLAG] == sk::kFlagLimit) {
+        rs.done = 1;
+        return NBX_OK;
+    }
+    if (g[NBX_S_FLAG] == 2.0) { rs.fell_back = rs.done = 1; return NBX_OK; }
+    // stagnation: two updates in a row without a twofold reduction
+    if (rs.last_true >= 0 && !(g[kSlotTrue] < 0.25 * rs.last_true)) ++rs.stalls;
+    else rs.stalls = 0;
+    rs.last_true = g[kSlotTrue];
+    if (rs.stalls >= 2 || rs.updates >= o.max_outer) {
+        rs.fell_back = rs.stalls >= 2;
+        rs.done = 1;
+    }
+    return NBX_OK;
+}
+
+int reliable_finish(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                    const ReliableState &rs, nbx_pcg_result *res, hipStream_t s)
+{
+    double *h = P->h_scal;
+    NBX_HIP(hipMemcpyAsync(h, P->scal32, sizeof(double) * NBX_SCAL_LEN, hipMemcpyDeviceToHost,
+                           s));
+    NBX_HIP(hipStreamSynchronize(s));
+    int total = (int)h[NBX_S_ITER];
+    const double bb = h[kSlotBB];
+    double relres = bb > 0 ? std::sqrt(h[kSlotTrue] / bb) : 0.0;
+    int flag = h[kSlotFinal] == 1.0 ? 1 : 0;
+    if (rs.fell_back && !flag) {
+        // the FP32 sequence broke down or stalled: FP64 PCG from the current x
+        double rb[2];
+        int st = residual_f64(P, b, x, P->r, rb, s);
+        if (st != NBX_OK) return st;
+        const double rel0 = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
+        double *rhs = nullptr, *d = nullptr;
+        if (hipMalloc(&rhs, sizeof(double) * (size_t)P->n) != hipSuccess) return NBX_ENOMEM;
+        if (hipMalloc(&d, sizeof(double) * (size_t)P->n) != hipSuccess) {
+            hipFree(rhs);
+            return NBX_ENOMEM;
+        }
+        NBX_HIP(hipMemcpyAsync(rhs, P->r, sizeof(double) * (size_t)P->n,
+                               hipMemcpyDeviceToDevice, s));
+        NBX_HIP(hipStreamSynchronize(s));   // pcg_f64 runs on the problem's own stream
+        nbx_pcg_opts o64 = o;
+        o64.prec = NBX_F64;
+        o64.rtol = rel0 > 0 ? o.rtol / rel0 : o.rtol;
+        o64.max_iter = o.max_iter - total;
+        nbx_pcg_result r64{};
+        st = pcg_f64(P, rhs, d, o64, &r64);
+        if (st == NBX_OK) {
+            hipLaunchKernelGGL(add_f64_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n, d, x);
+            st = residual_f64(P, b, x, P->r, rb, s);
+        }
+        NBX_HIP(hipStreamSynchronize(s));
+        hipFree(rhs);
+        hipFree(d);
+        if (st != NBX_OK) return st;
+        total += r64.iters;
+        relres = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
+        flag = relres <= o.rtol ? 1 : (r64.flag == 2 ? 2 : 0);
+    }
+    res->iters = total;
+    res->outer_iters = rs.updates;
+    res->relres = relres;
+    res->true_relres = relres;
+    res->fell_back = rs.fell_back;
+    res->flag = flag;
+    return NBX_OK;
+}
+
 static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
                               const nbx_pcg_opts &o, nbx_pcg_result *res)
 {
     hipStream_t s = P->ws;
     int st = prepare_inner(P, o.prec, s);
     if (st != NBX_OK) return st;
-    const GsPlan &gs = P->gs->plan;
-    const int nb = sk::red_blocks(P->n);
-    const double delta = (o.inner_rtol > 0 && o.inner_rtol < 1) ? o.inner_rtol : 0.1;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
     if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
                         P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(P->inner_fmt, P->N))) {
@@ -307,22 +419,11 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
-    // x = 0; r64 = b; <b,b>_c; FP32 state from b
-    NBX_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)P->n, s));
-    hipLaunchKernelGGL(sk::resid_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, b, x,
-                       gs.info, P->r, P->part3);
-    hipLaunchKernelGGL(sk::sum2_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3, P->tmp2);
-    hipLaunchKernelGGL((sk::init_kernel<float, double>), dim3(nb), dim3(sk::kRedThreads), 0, s,
-                       P->n, P->r, P->dinv32, gs.info, P->d32, P->r32, P->z32, P->p32, P->part3);
-    hipLaunchKernelGGL(sk::init_reduce_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3,
-                       P->scal32, delta, 0, o.max_iter);
-    hipLaunchKernelGGL(mixed_setup_kernel, dim3(1), dim3(1), 0, s, P->scal32, P->tmp2, o.rtol,
-                       delta);
-    NBX_LAUNCH_CHECK();
-    int updates = 0, fell_back = 0, stalls = 0;
-    double last_true = -1.0;
+    st = reliable_start(P, b, x, o, s);
+    if (st != NBX_OK) return st;
+    ReliableState rs;
     double *h = P->h_scal;
-    while (true) {
+    while (!rs.done) {
         // FP32 iterations until the segment's reduction, breakdown or limit
         while (true) {
             if (o.use_graph) {
@@ -336,76 +437,13 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
             NBX_HIP(hipStreamSynchronize(s));
             if (h[NBX_S_FLAG] != 0.0) break;
         }
-        if (h[kSlotFinal] == 1.0) break;             // zero right-hand side
-        if (h[NBX_S_FLAG] == 2.0) { fell_back = 1; break; }
-        // reliable update (also after the iteration limit, to report x)
-        hipLaunchKernelGGL(fold_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n, P->d32, x);
-        NBX_LAUNCH_CHECK();
-        st = ax_launch_f64(x, P->G, P->D, P->N, P->E, P->w, s);
+        st = reliable_step(P, b, x, o, h, rs, s);
         if (st != NBX_OK) return st;
-        st = dssum_launch<double>(gs, P->w, 1, s);
-        if (st != NBX_OK) return st;
-        const bool at_limit = h[NBX_S_FLAG] == sk::kFlagLimit;
-        hipLaunchKernelGGL(replace_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, b, P->w,
-                           P->dinv32, gs.info, P->r32, P->z32, P->part3);
-        hipLaunchKernelGGL(reliable_reduce_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3,
-                           P->scal32);
-        NBX_LAUNCH_CHECK();
-        NBX_HIP(hipMemcpyAsync(h, P->scal32, sizeof(double) * NBX_SCAL_LEN,
-                               hipMemcpyDeviceToHost, s));
-        NBX_HIP(hipStreamSynchronize(s));
-        ++updates;
-        if (h[kSlotFinal] == 1.0 || at_limit || h[NBX_S_FLAG] == sk::kFlagLimit) break;
-        if (h[NBX_S_FLAG] == 2.0) { fell_back = 1; break; }
-        // stagnation: two updates in a row without a twofold reduction
-        if (last_true >= 0 && !(h[kSlotTrue] < 0.25 * last_true)) ++stalls; else stalls = 0;
-        last_true = h[kSlotTrue];
-        if (stalls >= 2 || updates >= o.max_outer) { fell_back = stalls >= 2; break; }
     }
-    int total = (int)h[NBX_S_ITER];
-    const double bb = h[kSlotBB];
-    double relres = bb > 0 ? std::sqrt(h[kSlotTrue] / bb) : 0.0;
-    int flag = h[kSlotFinal] == 1.0 ? 1 : 0;
-    if (fell_back && !flag) {
-        // the FP32 sequence broke down or stalled: FP64 PCG from the current x
-        double rb[2];
-        st = residual_f64(P, b, x, P->r, rb, s);
-        if (st != NBX_OK) return st;
-        const double rel0 = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
-        double *rhs = nullptr, *d = nullptr;
-        if (hipMalloc(&rhs, sizeof(double) * (size_t)P->n) != hipSuccess) return NBX_ENOMEM;
-        if (hipMalloc(&d, sizeof(double) * (size_t)P->n) != hipSuccess) {
-            hipFree(rhs);
-            return NBX_ENOMEM;
-        }
-        NBX_HIP(hipMemcpyAsync(rhs, P->r, sizeof(double) * (size_t)P->n,
-                               hipMemcpyDeviceToDevice, s));
-        nbx_pcg_opts o64 = o;
-        o64.prec = NBX_F64;
-        o64.rtol = rel0 > 0 ? o.rtol / rel0 : o.rtol;
-        o64.max_iter = o.max_iter - total;
-        nbx_pcg_result r64{};
-        st = pcg_f64(P, rhs, d, o64, &r64);
-        if (st == NBX_OK) {
-            hipLaunchKernelGGL(add_f64_kernel, dim3(grid_for(P->n)), dim3(256), 0, s, P->n, d, x);
-            st = residual_f64(P, b, x, P->r, rb, s);
-        }
-        NBX_HIP(hipStreamSynchronize(s));
-        hipFree(rhs);
-        hipFree(d);
-        if (st != NBX_OK) return st;
-        total += r64.iters;
-        relres = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
-        flag = relres <= o.rtol ? 1 : (r64.flag == 2 ? 2 : 0);
-    }
+    st = reliable_finish(P, b, x, o, rs, res, s);
+    if (st != NBX_OK) return st;
     const auto t1 = std::chrono::steady_clock::now();
     res->seconds = std::chrono::duration<double>(t1 - t0).count();
-    res->iters = total;
-    res->outer_iters = updates;
-    res->relres = relres;
-    res->true_relres = relres;
-    res->fell_back = fell_back;
-    res->flag = flag;
     return NBX_OK;
 }
 

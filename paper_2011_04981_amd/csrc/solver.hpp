@@ -47,4 +47,24 @@ int pcg_mixed(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
 // P->inner_fmt.  Synchronous.
 int prepare_inner(nbx_problem *P, int fmt, hipStream_t s);
 
+// The mixed solver's reliable-update scheme (mixed_mode 0), in three steps
+// so that a batch can run the FP32 iterations of many problems together:
+// reliable_start sets x = 0 and the FP32 state from b (async on s); after
+// the FP32 iterations of a problem have stopped (h = its FP32 scalar block
+// as read on the host), reliable_step folds the correction into x, replaces
+// the residual by the FP64 one and applies the stop tests (synchronous on
+// s; rs.done once the solve is over); reliable_finish runs the FP64
+// fallback if the FP32 sequence broke down or stalled and fills res (all
+// but seconds).
+struct ReliableState {
+    int updates = 0, stalls = 0, fell_back = 0, done = 0;
+    double last_true = -1.0;
+};
+int reliable_start(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                   hipStream_t s);
+int reliable_step(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                  const double *h, ReliableState &rs, hipStream_t s);
+int reliable_finish(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
+                    const ReliableState &rs, nbx_pcg_result *res, hipStream_t s);
+
 }  // namespace nbx

@@ -65,6 +65,41 @@ def test_batched_bit_identical_to_standalone():
     assert lat[int(np.argmax(iters))] >= 0.99 * max(lat)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_mixed_batched_bit_identical_to_standalone(prec, graph):
+    """Mixed-precision batches (reliable updates): the FP32 iterations of all
+    problems run together and each problem's FP64 residual replacement
+    follows the standalone steps, so every problem's iterations, updates and
+    solution agree bit for bit with its standalone mixed solve."""
+    p = {"f32": nbx.F32, "f16": nbx.F16, "bf16": nbx.BF16}[prec]
+    probs = _problems()
+    kw = dict(rtol=1e-10, max_iter=6000, check_every=10, prec=p, use_graph=graph)
+    refs = []
+    for b, st in probs:
+        x, r = st.problem.pcg(st.b, **kw)
+        assert r.status == 0
+        refs.append((host(x), r.iters, r.outer_iters, r.fell_back))
+    xs, res, lat = nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                                   **kw)
+    for (b, st), (xr, it, outer, fb), x, r in zip(probs, refs, xs, res):
+        print(f"{prec} {b.name or b}: standalone {it} it / {outer} updates, "
+              f"batched {r.iters} / {r.outer_iters}")
+        assert r.status == 0 and r.flag == 1
+        assert (r.iters, r.outer_iters, r.fell_back) == (it, outer, fb)
+        assert np.array_equal(host(x), xr)
+        assert r.true_relres <= 2e-10
+    wall = res[0].seconds
+    assert all(0 < t <= wall * 1.05 for t in lat)
+
+
+def test_mixed_batched_refuses_restarted_refinement():
+    probs = _problems()[:2]
+    with pytest.raises(nbx.NbxError):
+        nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                        prec=nbx.F32, mixed_mode=1)
+
+
 def test_batched_matches_oracle():
     b = S.Brick(3, 2, 2, 8, ((0.05, 2, 2, 2),) * 3, "random", 21)
     f = S.rhs_values(b)
