@@ -93,6 +93,44 @@ def test_mixed_batched_bit_identical_to_standalone(prec, graph):
     assert all(0 < t <= wall * 1.05 for t in lat)
 
 
+def test_mixed_batched_breakdown_and_limit_are_per_problem():
+    """A batch holding an indefinite problem (negated factors: <p, Ap> < 0 at
+    once) next to ordinary ones: the indefinite one ends in breakdown after
+    its FP64 fallback broke down too, the others converge as they would
+    alone; a tiny iteration limit leaves every problem unconverged with the
+    FP64 true residual and solution of its standalone solve."""
+    probs = _problems()[:3]
+    b0, st0 = probs[0]
+    kw = dict(rtol=1e-10, max_iter=6000, check_every=10, prec=nbx.F16)
+    refs = []
+    for _, st in probs:
+        x, r = st.problem.pcg(st.b, **kw)
+        refs.append((host(x), r.iters, r.outer_iters))
+    bad = nbx.Problem(-st0.G, st0.D, b0.N, st0.gs)
+    plist = [st.problem for _, st in probs] + [bad]
+    blist = [st.b for _, st in probs] + [st0.b]
+    xs, res, lat = nbx.pcg_batched(plist, blist, **kw)
+    print(f"indefinite member: flag {res[3].flag}, {res[3].iters} it, "
+          f"fell back {res[3].fell_back}")
+    for (xr, it, outer), x, r in zip(refs, xs, res):
+        assert r.status == -5 and r.flag == 1 and r.true_relres <= 2e-10
+        assert (r.iters, r.outer_iters) == (it, outer)
+        assert np.array_equal(host(x), xr)
+    assert res[3].flag == 2 and res[3].fell_back == 1 and res[3].iters <= 5
+    assert np.all(np.isfinite(host(xs[3])))
+    # the iteration limit: CG residuals are not monotone, so the reported
+    # true residual is checked against the standalone solve, not against 1
+    kw = dict(rtol=1e-10, max_iter=12, check_every=5, prec=nbx.F32)
+    xs, res, lat = nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                                   **kw)
+    for (_, st), x, r in zip(probs, xs, res):
+        xr, rr = st.problem.pcg(st.b, **kw)
+        print(f"limit: {r.iters} it, flag {r.flag}, true relres {r.true_relres:.2e}")
+        assert r.status == 1 and r.flag == 0 and r.iters == rr.iters == 12
+        assert r.true_relres == rr.true_relres and np.isfinite(r.true_relres)
+        assert np.array_equal(host(x), host(xr))
+
+
 def test_mixed_batched_refuses_restarted_refinement():
     probs = _problems()[:2]
     with pytest.raises(nbx.NbxError):
