@@ -39,11 +39,18 @@ struct AxShape {
     // registers (6 PF values); the remaining slabs are loaded in the k
     // loop.  The whole column fits up to N = 10 in FP64 (12N VGPRs) and
     // N = 12 in FP32; larger elements keep the register file under 256.
+    // FP64 N = 12 takes 4 so that the kernel fits 168 VGPRs: three waves
+    // per SIMD, i.e. all three 3-wave workgroups that its LDS allows on a CU
+    // (4 more slabs in flight cost 15 % there); LDS holds the other large
+    // sizes to two waves per SIMD (or one), so they take as many slabs as
+    // fit without spilling (measured on 16-25 M nodes against 6 and 4
+    // slabs: 9-24 % faster at N = 11 and 13-15).
     template <typename T>
     static constexpr int pf()
     {
-        return sizeof(T) == sizeof(double) ? (N <= 10 ? N : (N <= 12 ? 6 : 4))
-                                           : (N <= 12 ? N : 8);
+        return sizeof(T) == sizeof(double)
+                   ? (N <= 10 ? N : (N == 11 ? 10 : (N == 12 ? 4 : 8)))
+                   : (N <= 12 ? N : 8);
     }
     // LDS of one block (three element slabs per element, D, reduction
     // slots) within the CU's 160 KB, and at most 1024 threads.
@@ -143,6 +150,7 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
     const size_t base = (size_t)e * N3;
     const GT *Ge = G + (size_t)e * 6 * N3;
     constexpr bool kHalfG = !std::is_same<GT, T>::value;
+    constexpr bool kPinD = sizeof(T) == sizeof(double) && N >= 11;
     T *su = s_u + el * N3, *swr = s_wr + el * N3, *sws = s_ws + el * N3;
 
     // 1. the column of u (or of z and the previous p) first ...
@@ -196,9 +204,17 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
             for (int m = 0; m < N; ++m) ur = ax_fma(Di[m], su[k * N2 + j * N + m], ur);
 #pragma unroll
             for (int m = 0; m < N; ++m) us = ax_fma(Dj[m], su[k * N2 + m * N + i], us);
+            // D[k][0..N-1] comes through the scalar cache; for large FP64
+            // elements the row's offset is tied to the previous slab's result,
+            // as the factor loads below are, so that the compiler does not
+            // hoist all N^2 uniform values to the top (more than the SGPR
+            // file: 146-372 SGPRs spilled to VGPR lanes at N = 11-16)
+            int dk = k * N;
+            if constexpr (kPinD)
+                if (k > 0) asm volatile("" : "+s"(dk) : "v"(wt[k - 1]));
 #pragma unroll
             for (int m = 0; m < N; ++m)
-                ut = ax_fma((T)Dg[k * N + m], uc[m], ut);
+                ut = ax_fma((T)Dg[dk + m], uc[m], ut);
             T g1, g2, g3, g4, g5, g6;
             if (k < PF) {
                 g1 = g[0][k]; g2 = g[1][k]; g3 = g[2][k]; g4 = g[3][k]; g5 = g[4][k]; g6 = g[5][k];
@@ -227,6 +243,7 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
     // 4. local_grad3_t: w = D^T wr + (ws D per slab) + wt D
     double pw = 0.0;
     T gsc = (T)1;
+    [[maybe_unused]] T last = 0;   // the previous output, which the next column of D waits for
     if constexpr (kHalfG) gsc = (T)gscale[e];
     {
         T DTi[N], DTj[N];
@@ -239,11 +256,15 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
             for (int m = 0; m < N; ++m) acc = ax_fma(DTi[m], swr[k * N2 + j * N + m], acc);
 #pragma unroll
             for (int m = 0; m < N; ++m) acc = ax_fma(DTj[m], sws[k * N2 + m * N + i], acc);
+            int dc = k;
+            if constexpr (kPinD)
+                if (k > 0) asm volatile("" : "+s"(dc) : "v"(last));
 #pragma unroll
             for (int m = 0; m < N; ++m)
-                acc = ax_fma((T)Dg[m * N + k], wt[m], acc);
+                acc = ax_fma((T)Dg[m * N + dc], wt[m], acc);
             if constexpr (kHalfG) acc *= gsc;
             if (valid) ax_st_nt(acc, w + base + k * N2 + tc);
+            last = acc;
             if constexpr (PCG) pw += (double)uc[k] * (double)acc;
         }
     }
