@@ -62,6 +62,14 @@ struct AxShape {
     }
 };
 
+// Large FP64 elements take the uniform entries of D slab by slab (see
+// ax_body); every other instantiation leaves their order to the compiler.
+template <typename T, int N>
+constexpr bool ax_pin_d()
+{
+    return sizeof(T) == sizeof(double) && N >= 11;
+}
+
 __device__ inline double ax_wave_sum(double v)
 {
 #pragma unroll
@@ -150,7 +158,7 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
     const size_t base = (size_t)e * N3;
     const GT *Ge = G + (size_t)e * 6 * N3;
     constexpr bool kHalfG = !std::is_same<GT, T>::value;
-    constexpr bool kPinD = sizeof(T) == sizeof(double) && N >= 11;
+    constexpr bool kPinD = ax_pin_d<T, N>();
     T *su = s_u + el * N3, *swr = s_wr + el * N3, *sws = s_ws + el * N3;
 
     // 1. the column of u (or of z and the previous p) first ...

@@ -54,20 +54,28 @@ struct BEntry {
 // Pointers read from a descriptor carry no address space, so every access
 // through them would compile to a flat one (flat loads count against both
 // the memory and the LDS wait counters, and uniform ones cannot use scalar
-// loads).  These casts restore what they are: global memory, and for the
-// read-only D, constant memory (uniform scalar loads).  Measured on the
-// batched N = 12 fused AX stage: 279 flat loads and 432 waits became the
-// standalone kernel's global/scalar loads and 246 waits.
-// (rebuilt from the integer value: a cast straight from the generic pointer
-// and back is folded away before the address spaces are inferred)
+// loads).  These casts restore what they are: global memory (rebuilt from
+// the integer value: a cast straight from the generic pointer and back is
+// folded away before address spaces are inferred).  Measured on the batched
+// N = 12 fused AX stage: 279 flat loads and 432 waits became the standalone
+// kernel's global and scalar loads and 249 waits.
 template <typename T>
 __device__ inline T *gp(T *p)
 {
     return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
 }
-__device__ inline const double *cp(const double *p)
+// D for an AX stage.  Where the kernel takes D slab by slab (ax_pin_d), its
+// uniform loads stay scalar only from constant memory (the ordering asm
+// would count as a possible store to global memory); elsewhere constant
+// memory would let the compiler hoist all N^2 values to the top (SGPR
+// spills in FP64, 214-256 VGPRs in FP32), so D stays global there.
+template <typename T, int N>
+__device__ inline const double *dp(const double *p)
 {
-    return (const double *)(const __attribute__((address_space(4))) double *)(uintptr_t)p;
+    if constexpr (ax_pin_d<T, N>())
+        return (const double *)(const __attribute__((address_space(4))) double *)(uintptr_t)p;
+    else
+        return gp(p);
 }
 
 __global__ void __launch_bounds__(sk::kRedThreads)
@@ -92,8 +100,8 @@ b_ax_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
 {
     const BEntry en = tab[blockIdx.x];
     const BDesc &d = desc[en.pid];
-    ax_body<double, N, EPB, true>(gp(d.z), gp(d.G), cp(d.D), gp(d.w), gp(d.p), gp(d.part1),
-                                  gp(d.scal), d.E, en.blk);
+    ax_body<double, N, EPB, true>(gp(d.z), gp(d.G), dp<double, N>(d.D), gp(d.w), gp(d.p),
+                                  gp(d.part1), gp(d.scal), d.E, en.blk);
 }
 
 __global__ void __launch_bounds__(1024) b_pap_kernel(const BDesc *__restrict__ desc)
@@ -162,9 +170,9 @@ b_ax32_kernel(const BDesc32 *__restrict__ desc, const BEntry *__restrict__ tab)
 {
     const BEntry en = tab[blockIdx.x];
     const BDesc32 &d = desc[en.pid];
-    ax_body<float, N, EPB, true, GT>(gp(d.z), gp(reinterpret_cast<const GT *>(d.G)), cp(d.D),
-                                     gp(d.w), gp(d.p), gp(d.part1), gp(d.scal), d.E, en.blk,
-                                     gp(d.gscale));
+    ax_body<float, N, EPB, true, GT>(gp(d.z), gp(reinterpret_cast<const GT *>(d.G)),
+                                     dp<float, N>(d.D), gp(d.w), gp(d.p), gp(d.part1),
+                                     gp(d.scal), d.E, en.blk, gp(d.gscale));
 }
 
 __global__ void __launch_bounds__(1024) b_pap32_kernel(const BDesc32 *__restrict__ desc)
