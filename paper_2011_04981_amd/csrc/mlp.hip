@@ -7,6 +7,7 @@
 // FP32 master weights with BF16 copies for the products.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -189,18 +190,41 @@ sum_partials_kernel(int nb, const double *__restrict__ part, double scale, doubl
     if (threadIdx.x == 0) *out = (s[0] + s[1] + s[2] + s[3]) * scale;
 }
 
-// out[n] = sum over rows of X[m][n] (FP32 or BF16 input), fixed order.
+// Column sums of X [M x N] (FP32 or BF16; M, N multiples of 64), deterministic, in two
+// launches: colsum_part_kernel sums 64 consecutive columns over a chunk of
+// 64 rows per workgroup (four row strides per column, coalesced across the
+// columns, then added in a fixed order) into part[M/64][N];
+// colsum_fin_kernel adds the chunks in order.  (One thread per column over
+// all rows left a batch of 1024 rows to one or two workgroups: 160-220 us a
+// call.)
 template <bool BF>
-__global__ void colsum_kernel(int M, int N, const void *__restrict__ X, int ldx,
-                              float *__restrict__ out)
+__global__ void __launch_bounds__(256)
+colsum_part_kernel(int N, const void *__restrict__ X, int ldx, float *__restrict__ part)
+{
+    __shared__ float s_red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + tx;
+    const int r0 = blockIdx.y * 64;
+    float s = 0.f;
+    for (int r = ty; r < 64; r += 4) {
+        const size_t q = (size_t)(r0 + r) * ldx + n;
+        s += BF ? bf2f(reinterpret_cast<const uint16_t *>(X)[q])
+                : reinterpret_cast<const float *>(X)[q];
+    }
+    s_red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0)
+        part[(size_t)blockIdx.y * N + n] = ((s_red[0][tx] + s_red[1][tx]) + s_red[2][tx]) +
+                                           s_red[3][tx];
+}
+
+__global__ void colsum_fin_kernel(int R, int N, const float *__restrict__ part,
+                                  float *__restrict__ out)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) {
-        const size_t q = (size_t)m * ldx + n;
-        s += BF ? bf2f(reinterpret_cast<const uint16_t *>(X)[q]) : reinterpret_cast<const float *>(X)[q];
-    }
+    for (int c = 0; c < R; ++c) s += part[(size_t)c * N + n];
     out[n] = s;
 }
 
@@ -264,6 +288,7 @@ struct nbx_mlp {
     uint16_t *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dH1 = nullptr, *dH2 = nullptr;
     float *Y = nullptr, *dY = nullptr;
     double *part = nullptr, *loss = nullptr;
+    float *cpart = nullptr;   // column-sum chunks [max_batch/64][max(n_hid, out_pad)]
     int step = 0;
     int64_t oW1() const { return 0; }
     int64_t ob1() const { return (int64_t)n_hid * in_pad; }
@@ -278,6 +303,17 @@ namespace nbx {
 namespace {
 
 constexpr int kLossBlocks = 1024;
+
+// out[N] = column sums of X [M x N] (M, N multiples of 64; part holds
+// M/64 x N floats).
+template <bool BF>
+void colsum(int M, int N, const void *X, int ldx, float *part, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(colsum_part_kernel<BF>, dim3(N / 64, M / 64), dim3(256), 0, s, N, X, ldx,
+                       part);
+    hipLaunchKernelGGL(colsum_fin_kernel, dim3((N + 255) / 256), dim3(256), 0, s, M / 64, N, part,
+                       out);
+}
 
 // Forward pass for B rows of X [B x in_pad] (BF16): H1, H2 (BF16) and
 // Y [B x out_pad] (FP32, biases added).
@@ -315,8 +351,7 @@ int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream
     if ((st = gemm(1, 0, EPI_F32, P->out_pad, P->n_hid, B, P->dYb, P->out_pad, P->H2, P->n_hid,
                    g + P->oW3(), P->n_hid, nullptr, 0, nullptr, nullptr, 0, s)) != NBX_OK)
         return st;
-    hipLaunchKernelGGL(colsum_kernel<false>, dim3((P->out_pad + 255) / 256), dim3(256), 0, s, B,
-                       P->out_pad, (const void *)P->dY, P->out_pad, g + P->ob3());
+    colsum<false>(B, P->out_pad, P->dY, P->out_pad, P->cpart, g + P->ob3(), s);
     if ((st = gemm(0, 0, EPI_RELU_GRAD_BF16, B, P->n_hid, P->out_pad, P->dYb, P->out_pad,
                    wb + P->oW3(), P->n_hid, nullptr, 0, P->dH2, P->n_hid, nullptr, P->H2,
                    P->n_hid, s)) != NBX_OK)
@@ -325,8 +360,7 @@ int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream
     if ((st = gemm(1, 0, EPI_F32, P->n_hid, P->n_hid, B, P->dH2, P->n_hid, P->H1, P->n_hid,
                    g + P->oW2(), P->n_hid, nullptr, 0, nullptr, nullptr, 0, s)) != NBX_OK)
         return st;
-    hipLaunchKernelGGL(colsum_kernel<true>, dim3((P->n_hid + 255) / 256), dim3(256), 0, s, B,
-                       P->n_hid, (const void *)P->dH2, P->n_hid, g + P->ob2());
+    colsum<true>(B, P->n_hid, P->dH2, P->n_hid, P->cpart, g + P->ob2(), s);
     if ((st = gemm(0, 0, EPI_RELU_GRAD_BF16, B, P->n_hid, P->n_hid, P->dH2, P->n_hid,
                    wb + P->oW2(), P->n_hid, nullptr, 0, P->dH1, P->n_hid, nullptr, P->H1,
                    P->n_hid, s)) != NBX_OK)
@@ -335,8 +369,7 @@ int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream
     if ((st = gemm(1, 0, EPI_F32, P->n_hid, P->in_pad, B, P->dH1, P->n_hid, X, P->in_pad,
                    g + P->oW1(), P->in_pad, nullptr, 0, nullptr, nullptr, 0, s)) != NBX_OK)
         return st;
-    hipLaunchKernelGGL(colsum_kernel<true>, dim3((P->n_hid + 255) / 256), dim3(256), 0, s, B,
-                       P->n_hid, (const void *)P->dH1, P->n_hid, g + P->ob1());
+    colsum<true>(B, P->n_hid, P->dH1, P->n_hid, P->cpart, g + P->ob1(), s);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
 }
@@ -394,7 +427,8 @@ extern "C" int nbx_mlp_create(int n_in, int n_hidden, int n_out, int max_batch, 
               hipMalloc(&P->Y, B * P->out_pad * 4) == hipSuccess &&
               hipMalloc(&P->dY, B * P->out_pad * 4) == hipSuccess &&
               hipMalloc(&P->part, kLossBlocks * sizeof(double)) == hipSuccess &&
-              hipMalloc(&P->loss, sizeof(double)) == hipSuccess;
+              hipMalloc(&P->loss, sizeof(double)) == hipSuccess &&
+              hipMalloc(&P->cpart, B / 64 * std::max(P->n_hid, P->out_pad) * 4) == hipSuccess;
     if (!ok) { nbx_mlp_destroy(P); return NBX_ENOMEM; }
     hipMemset(P->w, 0, np * 4); hipMemset(P->g, 0, np * 4);
     hipMemset(P->m, 0, np * 4); hipMemset(P->v, 0, np * 4); hipMemset(P->wb, 0, np * 2);
@@ -407,7 +441,7 @@ extern "C" int nbx_mlp_destroy(nbx_mlp *P)
     if (!P) return NBX_OK;
     hipFree(P->w); hipFree(P->g); hipFree(P->m); hipFree(P->v); hipFree(P->wb);
     hipFree(P->H1); hipFree(P->H2); hipFree(P->dH1); hipFree(P->dH2); hipFree(P->dYb);
-    hipFree(P->Y); hipFree(P->dY); hipFree(P->part); hipFree(P->loss);
+    hipFree(P->Y); hipFree(P->dY); hipFree(P->part); hipFree(P->loss); hipFree(P->cpart);
     delete P;
     return NBX_OK;
 }
