@@ -62,12 +62,13 @@ struct AxShape {
     }
 };
 
-// Large FP64 elements take the uniform entries of D slab by slab (see
-// ax_body); every other instantiation leaves their order to the compiler.
+// Large elements take the uniform entries of D slab by slab (see ax_body):
+// FP64 from N = 11, FP32 arithmetic from N = 13, where the factor loads are
+// pinned too; smaller ones leave their order to the compiler.
 template <typename T, int N>
 constexpr bool ax_pin_d()
 {
-    return sizeof(T) == sizeof(double) && N >= 11;
+    return sizeof(T) == sizeof(double) ? N >= 11 : N >= 13;
 }
 
 __device__ inline double ax_wave_sum(double v)
@@ -212,11 +213,12 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
             for (int m = 0; m < N; ++m) ur = ax_fma(Di[m], su[k * N2 + j * N + m], ur);
 #pragma unroll
             for (int m = 0; m < N; ++m) us = ax_fma(Dj[m], su[k * N2 + m * N + i], us);
-            // D[k][0..N-1] comes through the scalar cache; for large FP64
+            // D[k][0..N-1] comes through the scalar cache; for large
             // elements the row's offset is tied to the previous slab's result,
             // as the factor loads below are, so that the compiler does not
             // hoist all N^2 uniform values to the top (more than the SGPR
-            // file: 146-372 SGPRs spilled to VGPR lanes at N = 11-16)
+            // file: 146-436 SGPRs spilled to VGPR lanes at N = 11-16 in FP64,
+            // 13-16 in FP32)
             int dk = k * N;
             if constexpr (kPinD)
                 if (k > 0) asm volatile("" : "+s"(dk) : "v"(wt[k - 1]));
