@@ -93,6 +93,35 @@ def test_mixed_batched_bit_identical_to_standalone(prec, graph):
     assert all(0 < t <= wall * 1.05 for t in lat)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_batched_large_orders_bit_identical(prec):
+    """Large elements take the uniform entries of D slab by slab (FP64 from
+    N = 11, FP32 arithmetic from N = 13), which the batched stages then read
+    from constant memory instead of global: batched solves of orders 11-16
+    must still equal the standalone ones bit for bit."""
+    p = {"f64": nbx.F64, "f32": nbx.F32, "f16": nbx.F16}[prec]
+    specs = [S.Brick(2, 2, 1, 11, ((0.04, 2, 2, 2),) * 3, "random", 31),
+             S.Brick(2, 1, 1, 13, ((0.03, 2, 2, 2),) * 3, "random", 32),
+             S.Brick(1, 2, 1, 14, S.NO_DEFORM, "sine", 0),
+             S.Brick(1, 1, 2, 16, ((0.02, 2, 2, 2),) * 3, "random", 33),
+             S.Brick(2, 2, 2, 12, ((0.05, 2, 2, 2),) * 3, "random", 34)]
+    sets = []
+    for b in specs:
+        f = torch.as_tensor(S.rhs_values(b)).cuda() if b.rhs == "random" else None
+        sets.append(nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array(), f=f))
+    kw = dict(rtol=1e-10, max_iter=8000, check_every=10, prec=p)
+    refs = []
+    for st in sets:
+        x, r = st.problem.pcg(st.b, **kw)
+        assert r.status == 0
+        refs.append((host(x), r.iters, r.outer_iters))
+    xs, res, lat = nbx.pcg_batched([st.problem for st in sets], [st.b for st in sets], **kw)
+    for b, (xr, it, outer), x, r in zip(specs, refs, xs, res):
+        print(f"{prec} N={b.N}: standalone {it} it, batched {r.iters}")
+        assert r.flag == 1 and (r.iters, r.outer_iters) == (it, outer)
+        assert np.array_equal(host(x), xr)
+
+
 def test_mixed_batched_breakdown_and_limit_are_per_problem():
     """A batch holding an indefinite problem (negated factors: <p, Ap> < 0 at
     once) next to ordinary ones: the indefinite one ends in breakdown after
