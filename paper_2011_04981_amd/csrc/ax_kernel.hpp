@@ -41,10 +41,10 @@ struct AxShape {
     // N = 12 in FP32; larger elements keep the register file under 256.
     // FP64 N = 12 takes 4 so that the kernel fits 168 VGPRs: three waves
     // per SIMD, i.e. all three 3-wave workgroups that its LDS allows on a CU
-    // (4 more slabs in flight cost 15 % there); LDS holds the other large
-    // sizes to two waves per SIMD (or one), so they take as many slabs as
-    // fit without spilling (measured on 16-25 M nodes against 6 and 4
-    // slabs: 9-24 % faster at N = 11 and 13-15).
+    // (6 slabs, 190 VGPRs, ran 19 % slower there); LDS holds the other
+    // large sizes to two waves per SIMD (or one), so they take as many slabs
+    // as fit without spilling (measured on 16-25 M nodes: 3-9 % faster than
+    // with 4 slabs at N = 11 and 13-16).
     template <typename T>
     static constexpr int pf()
     {
