@@ -110,13 +110,13 @@ __global__ void __launch_bounds__(1024) b_pap_kernel(const BDesc *__restrict__ d
     sk::pap_reduce_body(d.nb1, gp(d.part1), gp(d.scal));
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kGsThreads)
 b_dssum_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
 {
     const BEntry en = tab[blockIdx.x];
     const BDesc &d = desc[en.pid];
     if (gp(d.scal)[NBX_S_FLAG] != 0.0) return;
-    const int32_t g = en.blk * 256 + threadIdx.x;
+    const int32_t g = en.blk * kGsThreads + threadIdx.x;
     if (g < d.n_groups) dssum_group<double>(g, gp(d.off), gp(d.idx), gp(d.gflag), gp(d.w), 1);
 }
 
@@ -181,13 +181,13 @@ __global__ void __launch_bounds__(1024) b_pap32_kernel(const BDesc32 *__restrict
     sk::pap_reduce_body(d.nb1, gp(d.part1), gp(d.scal));
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kGsThreads)
 b_dssum32_kernel(const BDesc32 *__restrict__ desc, const BEntry *__restrict__ tab)
 {
     const BEntry en = tab[blockIdx.x];
     const BDesc32 &d = desc[en.pid];
     if (gp(d.scal)[NBX_S_FLAG] != 0.0) return;
-    const int32_t g = en.blk * 256 + threadIdx.x;
+    const int32_t g = en.blk * kGsThreads + threadIdx.x;
     if (g < d.n_groups) dssum_group<float>(g, gp(d.off), gp(d.idx), gp(d.gflag), gp(d.w), 1);
 }
 
@@ -315,7 +315,8 @@ int enqueue_batch_iters(const BatchPlan &B, int n_iter, hipStream_t s)
         }
         hipLaunchKernelGGL(b_pap_kernel, dim3(B.nprob), dim3(1024), 0, s, B.desc);
         if (B.n_gs > 0)
-            hipLaunchKernelGGL(b_dssum_kernel, dim3(B.n_gs), dim3(256), 0, s, B.desc, B.t_gs);
+            hipLaunchKernelGGL(b_dssum_kernel, dim3(B.n_gs), dim3(kGsThreads), 0, s, B.desc,
+                               B.t_gs);
         if (B.n_mask > 0)
             hipLaunchKernelGGL(b_mask_kernel, dim3(B.n_mask), dim3(256), 0, s, B.desc, B.t_mask);
         hipLaunchKernelGGL(b_update_kernel, dim3(B.n_vec), dim3(sk::kRedThreads), 0, s, B.desc,
@@ -354,7 +355,8 @@ int enqueue_batch32_iters(const BatchPlan32 &B, int n_iter, hipStream_t s)
         }
         hipLaunchKernelGGL(b_pap32_kernel, dim3(B.nprob), dim3(1024), 0, s, B.desc);
         if (B.n_gs > 0)
-            hipLaunchKernelGGL(b_dssum32_kernel, dim3(B.n_gs), dim3(256), 0, s, B.desc, B.t_gs);
+            hipLaunchKernelGGL(b_dssum32_kernel, dim3(B.n_gs), dim3(kGsThreads), 0, s, B.desc,
+                               B.t_gs);
         if (B.n_mask > 0)
             hipLaunchKernelGGL(b_mask32_kernel, dim3(B.n_mask), dim3(256), 0, s, B.desc,
                                B.t_mask);
@@ -400,7 +402,7 @@ int pcg_batched_mixed(nbx_problem *const *probs, const double *const *b, double 
         d.nb3 = sk::red_blocks(P->n, sk::Vec<float>::W);
         d.pad = 0;
         for (int q = 0; q < d.nb3; ++q) tv.push_back({p, q});
-        for (int q = 0; q < (g.n_groups + 255) / 256; ++q) tg.push_back({p, q});
+        for (int q = 0; q < (g.n_groups + kGsThreads - 1) / kGsThreads; ++q) tg.push_back({p, q});
         for (int q = 0; q < (g.n_mask_only + 255) / 256; ++q) tm.push_back({p, q});
     }
     int st;
@@ -550,7 +552,7 @@ extern "C" int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b
         d.nb3 = sk::red_blocks(P->n);
         d.pad = 0;
         for (int q = 0; q < d.nb3; ++q) tv.push_back({p, q});
-        for (int q = 0; q < (g.n_groups + 255) / 256; ++q) tg.push_back({p, q});
+        for (int q = 0; q < (g.n_groups + kGsThreads - 1) / kGsThreads; ++q) tg.push_back({p, q});
         for (int q = 0; q < (g.n_mask_only + 255) / 256; ++q) tm.push_back({p, q});
     }
     int st;

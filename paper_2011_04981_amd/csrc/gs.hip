@@ -21,11 +21,11 @@ namespace {
 // threads after them zero the unshared Dirichlet nodes (one launch for
 // both steps).
 template <typename T>
-__global__ void dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off,
-                             const int32_t *__restrict__ idx, const uint8_t *__restrict__ gflag,
-                             T *__restrict__ v, int apply_mask, int32_t n_mask,
-                             const int32_t *__restrict__ mask_idx,
-                             const double *__restrict__ flag)
+__global__ void __launch_bounds__(kGsThreads)
+dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
+             const uint8_t *__restrict__ gflag, T *__restrict__ v, int apply_mask,
+             int32_t n_mask, const int32_t *__restrict__ mask_idx,
+             const double *__restrict__ flag)
 {
     if (flag && *flag != 0.0) return;   // uniform: solve already finished
     // XCD-aware mapping: workgroups are dealt to the 8 XCDs round-robin, so
@@ -75,8 +75,8 @@ int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const do
 {
     const int64_t nt = (int64_t)gs.n_groups + (apply_mask ? gs.n_mask_only : 0);
     if (nt > 0) {
-        const int64_t nb = ((nt + 255) / 256 + 7) / 8 * 8;   // a multiple of the 8 XCDs
-        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)nb), dim3(256), 0, s,
+        const int64_t nb = ((nt + kGsThreads - 1) / kGsThreads + 7) / 8 * 8;   // 8 XCDs
+        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)nb), dim3(kGsThreads), 0, s,
                            gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask,
                            gs.n_mask_only, gs.mask_idx, flag);
         NBX_LAUNCH_CHECK();

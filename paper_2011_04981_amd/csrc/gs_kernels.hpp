@@ -6,6 +6,13 @@
 
 namespace nbx {
 
+// Threads per workgroup of the exchange launches.  The largest workgroup
+// measured best on the 32^3 brick at N = 10 (one FP64 pass 226 / 219 / 210 /
+// 199 / 184 us at 64 / 128 / 256 / 512 / 1024 threads; FP64 solve 1.736 ->
+// 1.690 s, FP16-G mixed solve 1.130 -> 1.086 s against 256): a CU then
+// walks a longer contiguous run of groups, whose copies share lines.
+constexpr int kGsThreads = 1024;
+
 // Group g: s = sum of v over the group's local indices in ascending order,
 // then s (or 0 for a Dirichlet group when apply_mask) to every copy.
 template <typename T>
