@@ -391,7 +391,8 @@ int nbx_lp_samples(nbx_lp *lp, const double *r, const double *xstar, const doubl
                    const int32_t *elems, int nsel, void *X, float *T, void *stream);
 /* Copies the recurrence residual of the problem's last solve. Async. */
 int nbx_problem_residual(nbx_problem *p, double *r, void *stream);
-/* Flexible PCG (Notay: beta = <r', z' - z> / <r, z>) with M from x = 0.  If
+/* Flexible PCG (Notay 2000, one stored direction: beta = -<z', A p> / <p, A p>,
+ * each new direction A-orthogonal to the last) with M from x = 0.  If
  * it breaks down or reaches opts->max_iter (pass the Jacobi-PCG iteration
  * count to enforce "no worse than Jacobi") without meeting rtol, Jacobi-PCG
  * finishes the solve from the current x (from x = 0 if the flexible

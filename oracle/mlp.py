@@ -5,9 +5,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  The network is not in
 the paper; this follows the textbook definitions: a 3-layer perceptron
 y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, the chain rule for its gradients
 (hand-written, pinned by central finite differences), Adam (Kingma & Ba
-2015, pinned by its first-step property), and flexible PCG (Notay 2000:
-beta = <r_new, z_new - z_old> / <r_old, z_old>, which equals PCG for a fixed
-SPD preconditioner).
+2015, pinned by its first-step property), and flexible PCG (Notay 2000,
+truncated to one previous direction: the new preconditioned residual is
+made A-orthogonal to the last direction, beta = -<z_new, A p> / <p, A p>,
+which equals PCG's beta for a fixed SPD preconditioner).
 
 Parameters use one flat arena: W1[hid][in_pad], b1[hid], W2[hid][hid],
 b2[hid], W3[out_pad][hid], b3[out_pad] (row-major W[out][in]).
@@ -121,13 +122,15 @@ class FpcgBreakdown(ArithmeticError):
         self.iteration = iteration
 
 
-def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
-    """Flexible preconditioned CG with c-weighted dots:
-    r = b - A x, z = M(r), p = z; per iteration
+def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10, on_step=None):
+    """Flexible preconditioned CG with c-weighted dots (Notay 2000 with one
+    stored direction): r = b - A x, z = M(r), p = z; per iteration
     w = A p, alpha = <r,z>/<p,w>, x += alpha p, r -= alpha w, z' = M(r),
-    beta = <r, z' - z> / <r_old, z>, p = z' + beta p.
-    Returns (x, iterations, relative residual history); raises
-    FpcgBreakdown when <r, z> or <p, w> is not positive."""
+    beta = -<z', w> / <p, w>, p = z' + beta p, so that every new direction
+    is A-orthogonal to the previous one whatever M does.  (For a fixed
+    symmetric M this is PCG's <r', z'> / <r, z>.)  ``on_step(k, p, w)`` sees
+    each direction and its image.  Returns (x, iterations, relative residual
+    history); raises FpcgBreakdown when <r, z> or <p, w> is not positive."""
     def dot(a, b_):
         return float(np.sum(c * a * b_))
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -141,6 +144,8 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
         raise FpcgBreakdown(0)
     for k in range(max_iter):
         w = apply_A(p)
+        if on_step is not None:
+            on_step(k, p, w)
         pw = dot(p, w)
         if not pw > 0:
             raise FpcgBreakdown(k)
@@ -151,13 +156,11 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10):
         hist.append(rel)
         if rel <= rtol:
             return x, k + 1, np.array(hist)
-        zn = precond(r)
-        rho_new = dot(r, zn)
-        if not rho_new > 0:
+        z = precond(r)
+        rho = dot(r, z)
+        if not rho > 0:
             raise FpcgBreakdown(k + 1)
-        beta = (rho_new - dot(r, z)) / rho
-        rho = rho_new
-        z = zn
+        beta = -dot(z, w) / pw
         p = z + beta * p
     return x, max_iter, np.array(hist)
 

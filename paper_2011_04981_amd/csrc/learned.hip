@@ -9,8 +9,9 @@
 // diagonal factors, and f the 3-layer network of mlp.hip (BF16 matrix-core
 // products, FP32 accumulation).  c = 1/multiplicity averages the element
 // outputs at shared nodes.  A network that outputs zero gives Jacobi back.
-// M is nonlinear, so the outer iteration is flexible PCG (Notay 2000:
-// beta = <r_new, z_new - z_old> / <r_old, z_old>).  Training pairs come from
+// M is nonlinear, so the outer iteration is flexible PCG (Notay 2000, one
+// stored direction: beta = -<z_new, A p> / <p, A p> makes each new direction
+// A-orthogonal to the previous one).  Training pairs come from
 // the FP64 solver: T_e = (e_e - dinv r_e) / s_e with e = x* - x_k.
 #include "solver.hpp"
 #include "solver_kernels.hpp"
@@ -111,11 +112,13 @@ __global__ void lp_combine_kernel(int N3, int out_pad, int64_t n, const float *_
     }
 }
 
-// z_new = dinv r + zl; partials of <r, z_new>_c and <r, z_old>_c; z = z_new.
+// z_new = dinv r + zl; partials of <r, z_new>_c and <z_new, w>_c (w = A p
+// of the step just taken; not read on the first application); z = z_new.
 __global__ void __launch_bounds__(sk::kRedThreads)
 lp_dots_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
                const double *__restrict__ zl, const uint8_t *__restrict__ info,
-               double *__restrict__ z, double *__restrict__ part, const double *__restrict__ scal)
+               const double *__restrict__ w, int first, double *__restrict__ z,
+               double *__restrict__ part, const double *__restrict__ scal)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     double a = 0, b = 0;
@@ -124,14 +127,14 @@ lp_dots_kernel(int64_t n, const double *__restrict__ r, const double *__restrict
         const double c = sk::cw(info[l]), rl = r[l];
         const double zn = dinv[l] * rl + zl[l];
         a += c * rl * zn;
-        b += c * rl * z[l];
+        if (!first) b += c * zn * w[l];
         z[l] = zn;
     }
     sk::block_sum2(a, b);
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = b; }
 }
 
-// beta = (<r,z_new> - <r,z_old>) / rho (0 on the first application);
+// beta = -<z_new, w> / <p, w> (0 on the first application);
 // rho = <r, z_new>; breakdown if it is not positive.
 __global__ void __launch_bounds__(1024)
 lp_beta_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal, int first)
@@ -144,13 +147,13 @@ lp_beta_kernel(int nb, const double *__restrict__ part, double *__restrict__ sca
     if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double rzn = 0, rzo = 0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { rzn += s[0][q]; rzo += s[1][q]; }
-        if (!(rzn > 0.0) || !isfinite(rzn) || !isfinite(rzo)) {
+        double rzn = 0, zw = 0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { rzn += s[0][q]; zw += s[1][q]; }
+        if (!(rzn > 0.0) || !isfinite(rzn) || !isfinite(zw)) {
             scal[NBX_S_FLAG] = 2.0;
             return;
         }
-        scal[NBX_S_BETA] = first ? 0.0 : (rzn - rzo) / scal[NBX_S_RHO];
+        scal[NBX_S_BETA] = first ? 0.0 : -zw / scal[NBX_S_PAP];
         scal[NBX_S_RHO] = rzn;
     }
 }
@@ -302,7 +305,7 @@ int enqueue_precond(nbx_lp *L, double *scal, int first, hipStream_t s)
     if (st != NBX_OK) return st;
     const int nb = sk::red_blocks(P->n);
     hipLaunchKernelGGL(lp_dots_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, P->r,
-                       P->dinv, L->zl, P->gs->plan.info, P->z, L->part4, scal);
+                       P->dinv, L->zl, P->gs->plan.info, P->w, first, P->z, L->part4, scal);
     hipLaunchKernelGGL(lp_beta_kernel, dim3(1), dim3(1024), 0, s, nb, L->part4, scal, first);
     NBX_LAUNCH_CHECK();
     return NBX_OK;

@@ -75,6 +75,38 @@ def test_fpcg_with_jacobi_equals_pcg():
     assert np.abs(x - ref.x).max() <= 1e-9 * np.abs(ref.x).max()
 
 
+def test_fpcg_keeps_directions_conjugate_under_a_varying_preconditioner():
+    """Notay's flexible CG with one stored direction A-orthogonalises each new
+    preconditioned residual against the previous direction, so consecutive
+    directions stay A-conjugate even when M changes every step.  A diagonal
+    preconditioner dinv (1 + 0.8 u_k), u_k ~ U[-1, 1] drawn afresh per step
+    (averaged over shared copies, so z stays consistent), is SPD at every
+    step but different each time: PCG's beta <r', z'>/<r, z> loses conjugacy
+    (and does not converge in 5000 steps on this mesh), as does the variant
+    <r', z' - z>/<r, z>; both fail this test."""
+    P = O.setup(S.scaled_c2_brick(3, 6))
+    rng = np.random.default_rng(11)
+    draws = []
+
+    def varying(r):
+        u = rng.uniform(-1.0, 1.0, size=P.n)
+        draws.append(1)
+        return O.mask(P.bnd, P.gs.dssum(P.c * P.dinv * (1.0 + 0.8 * u) * r))
+
+    steps = []
+    x, it, hist = M.fpcg(P.apply_A, varying, P.b, P.c, max_iter=2000, rtol=1e-10,
+                         on_step=lambda k, p, w: steps.append((p.copy(), w.copy())))
+    assert hist[-1] <= 1e-10 and it < 2000
+    # the solution is the assembled system's (checked by the oracle's PCG)
+    ref = O.pcg(P, max_iter=2000, rtol=1e-12)
+    assert np.abs(x - ref.x).max() <= 1e-8 * np.abs(ref.x).max()
+    for (p0, w0), (p1, w1) in zip(steps[:40], steps[1:41]):
+        a01 = O.wdot(P.c, p1, w0)
+        n0 = np.sqrt(O.wdot(P.c, p0, w0))
+        n1 = np.sqrt(O.wdot(P.c, p1, w1))
+        assert abs(a01) <= 1e-8 * n0 * n1, abs(a01) / (n0 * n1)
+
+
 def test_fpcg_detects_breakdown():
     # M = -Jacobi is negative definite: <r, M r> < 0 at once
     P = O.setup(S.scaled_c2_brick(2, 4))
