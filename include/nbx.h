@@ -22,15 +22,19 @@
  *
  * Layouts (Section II-B, Listing 1, column-major u(i,j,k,e)):
  *   u, w, vectors : [E][N][N][N], i fastest: u[((e*N + k)*N + j)*N + i]
- *   G             : per element three planes of factor pairs, (g1,g2),
- *                   (g3,g4), (g5,g6), one pair per node: factor f (0-based,
+ *   G             : [E][6][N^3], one plane per factor: factor f (0-based,
  *                   g_(f+1) of the listing, the symmetric matrix
  *                   [[g1,g2,g3],[g2,g4,g5],[g3,g5,g6]]) of node q of
- *                   element e at G[((e*3 + f/2)*N^3 + q)*2 + f%2], written
- *                   [E][3][N^3][2] below (6*E*N^3 values).  A lane of the
- *                   operator fetches a pair with one 16-byte load.
- *                   nbx_pair_factors converts from [E][6][N^3] planes,
- *                   nbx_repack_g_aos_to_soa from the listing's g(6,N^3,E).
+ *                   element e at G[(e*6 + f)*N^3 + q] (6*E*N^3 values).
+ *                   nbx_repack_g_aos_to_soa converts from the listing's
+ *                   g(6,N^3,E), the six factors of a node contiguous.
+ *   Gp            : the same factors as three planes of factor pairs per
+ *                   element, (g1,g2), (g3,g4), (g5,g6), one pair per node,
+ *                   at Gp[((e*3 + f/2)*N^3 + q)*2 + f%2], written
+ *                   [E][3][N^3][2]: the layout inside a problem, where a
+ *                   lane of the fused operator fetches a pair with one
+ *                   16-byte load.  Only nbx_ax_paired / nbx_ax_paired_tiled
+ *                   take it; nbx_pair_factors converts G to it.
  *   D             : N x N row-major, D[a*N + b] = l_b'(xi_a) (the
  *                   listing's dxm1; its transpose dxtm1 is derived inside)
  *   N             : Gauss-Lobatto-Legendre nodes per direction (degree N-1),
@@ -97,9 +101,10 @@ int nbx_deriv(int N, double *D_host);
  * deform_host[12] = {A_x,k1,k2,k3, A_y,k1,k2,k3, A_z,k1,k2,k3}: coordinate
  * c of the node at undeformed position (X,Y,Z) is
  * C + A_c sin(k1 pi X) sin(k2 pi Y) sin(k3 pi Z).  Outputs (device):
- * G[E][3][N^3][2] = w_i w_j w_k det(J) (grad r_a . grad r_b) from
- * isoparametric derivatives, bm[E][N^3] = w_i w_j w_k det(J) (may be NULL),
- * xyz[3][E][N^3] node coordinates (may be NULL). */
+ * G[E][6][N^3] = w_i w_j w_k det(J) (grad r_a . grad r_b) from
+ * isoparametric derivatives, in the [E][6][N^3] layout above,
+ * bm[E][N^3] = w_i w_j w_k det(J) (may be NULL), xyz[3][E][N^3] node
+ * coordinates (may be NULL). */
 int nbx_geom_brick(int ex, int ey, int ez, int N, const double *deform_host,
                    double *G, double *bm, double *xyz, void *stream);
 
@@ -110,12 +115,13 @@ int nbx_geom(const double *xyz, int N, int64_t E, double *G, double *bm, void *s
 /* Repacks geometric factors given in the layout of the operator's g
  * argument (Section II-B: g(6, N^3, E), the six factors of a node
  * contiguous, g_aos[(e*N^3 + p)*6 + f]) into the layout every other call
- * takes, planes of factor pairs (g_soa[((e*3 + f/2)*N^3 + p)*2 + f%2]).
- * nbx_pair_factors does the same from per-factor planes, [E][6][N^3]
- * (g6[(e*6 + f)*N^3 + p]).  f = 0..5 for g1..g6.  Device arrays of 6*E*N^3
- * doubles each, caller-owned; they must not overlap (NBX_EINVAL).  Async
- * on stream, no allocation; E = 0 is a no-op.  NBX_EINVAL for N outside
- * [2, 16], E < 0 or a null pointer. */
+ * takes, one plane per factor (g_soa[(e*6 + f)*N^3 + p]).
+ * nbx_pair_factors turns such planes, g6 = G[E][6][N^3], into the factor
+ * pairs of nbx_ax_paired (g_pairs[((e*3 + f/2)*N^3 + p)*2 + f%2]).
+ * f = 0..5 for g1..g6.  Device arrays of 6*E*N^3 doubles each,
+ * caller-owned; they must not overlap (NBX_EINVAL).  Async on stream, no
+ * allocation; E = 0 is a no-op.  NBX_EINVAL for N outside [2, 16], E < 0 or
+ * a null pointer. */
 int nbx_repack_g_aos_to_soa(const double *g_aos, double *g_soa, int N, int64_t E,
                             void *stream);
 int nbx_pair_factors(const double *g6, double *g_pairs, int N, int64_t E, void *stream);
@@ -128,11 +134,12 @@ int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host, uint8_t *bnd
 /* ---------------------------------------------------------------- AX --
  * w_e = D^T G_e D u_e for every element e in [0,E) (Section II-B,
  * Listing 1: local_grad3, the geometric contraction, local_grad3_t).
- * Async; no allocation.  prec selects the storage and arithmetic type of
- * u, G, w: NBX_F64 (double), NBX_F32 (float, FP32 arithmetic).  D is always
- * double (converted inside).  u and w must not overlap.  E == 0 is a no-op.
- * NBX_EINVAL for null pointers, N outside [2,16] or E < 0;
- * NBX_EUNSUPPORTED for other precisions. */
+ * G is [E][6][N^3] (the listing's g with the element and node indices
+ * outermost, see Layouts).  Async; no allocation.  prec selects the storage
+ * and arithmetic type of u, G, w: NBX_F64 (double), NBX_F32 (float, FP32
+ * arithmetic).  D is always double (converted inside).  u and w must not
+ * overlap.  E == 0 is a no-op.  NBX_EINVAL for null pointers, N outside
+ * [2,16] or E < 0; NBX_EUNSUPPORTED for other precisions. */
 int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
            void *w, void *stream);
 
@@ -143,7 +150,16 @@ int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64
 int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
                  void *w, int epb, void *stream);
 
-/* The tile nbx_ax uses for (prec, N) (process-wide; set by the
+/* The same operator on factor pairs Gp[E][3][N^3][2] (see Layouts): three
+ * 16-byte factor loads per node instead of six 8-byte ones, the form the
+ * solvers use inside a problem.  Results are bit-identical to nbx_ax /
+ * nbx_ax_tiled on the same factors.  Arguments and errors as there. */
+int nbx_ax_paired(int prec, const void *u, const void *Gp, const double *D, int N, int64_t E,
+                  void *w, void *stream);
+int nbx_ax_paired_tiled(int prec, const void *u, const void *Gp, const double *D, int N,
+                        int64_t E, void *w, int epb, void *stream);
+
+/* The tile nbx_ax and nbx_ax_paired use for (prec, N) (process-wide; set by the
  * autotuner).  get returns epb or a negative status; set refuses a tile
  * that does not fit (NBX_EUNSUPPORTED, as nbx_ax_tiled).  prec NBX_F64,
  * NBX_F32, or NBX_F16 / NBX_BF16 for the one table of the 16-bit-G kernels
@@ -168,7 +184,7 @@ int nbx_pcg_get_tile(int prec, int N);
  * nearest-even, first to FP32, then to gprec = NBX_F16 (IEEE binary16) or
  * NBX_BF16 (bfloat16), stored at G16[((e*3 + f/2)*N^3 + q)*2 + f%2]: three
  * planes per element of 32-bit words holding the factor pairs (g1,g2),
- * (g3,g4), (g5,g6) of a node, low half first.  G (FP64, [E][3][N^3][2]), G16
+ * (g3,g4), (g5,g6) of a node, low half first.  G (FP64, [E][6][N^3]), G16
  * (6*E*N^3 16-bit words, 4-byte aligned) and gscale ([E] float) are device
  * arrays.  Async.
  *
@@ -224,10 +240,12 @@ int nbx_rhs(nbx_gs *gs, const double *bm, const double *f, int64_t n_local, doub
 /* --------------------------------------------------------------- PCG -- */
 typedef struct nbx_problem nbx_problem;
 
-/* Binds G, D, N, E and a gather-scatter plan (all remain caller-owned and
- * must outlive the problem), computes dinv on the device and allocates the
- * solver workspace (four vectors, reduction partials, scalars).
- * Synchronous.  NBX_ENOMEM if device memory runs out. */
+/* Binds D, N, E and a gather-scatter plan (caller-owned; they must outlive
+ * the problem), copies G ([E][6][N^3]) into the problem's own factor-pair
+ * layout (6*E*N^3 doubles; G itself may be freed afterwards), computes dinv
+ * on the device and allocates the solver workspace (four vectors,
+ * reduction partials, scalars).  Synchronous.  NBX_ENOMEM if device memory
+ * runs out. */
 int nbx_problem_create(const double *G, const double *D, int N, int64_t E, nbx_gs *gs,
                        nbx_problem **out, void *stream);
 int nbx_problem_destroy(nbx_problem *p);
@@ -365,40 +383,89 @@ int nbx_mlp_grad(nbx_mlp *mlp, const void *X, const float *T, int B, double *los
 int nbx_mlp_train_step(nbx_mlp *mlp, const void *X, const float *T, int B, float lr,
                        double *loss, void *stream);
 
-/* ------------------------------------------ learned preconditioner (flexible CG) --
- * M(r) = dinv r + mask(dssum(c * s_e * f(x_e))): per element e the network
- * f (n_in = N^3 + 6, n_out = N^3) sees x_e = [r_e / ||r_e||, the six
- * element-mean geometric factors divided by gd_e] and its output is scaled
- * by s_e = ||r_e|| / gd_e (gd_e = element mean of g1, g4, g6); c =
- * 1/multiplicity.  Zero network output gives back the Jacobi
- * preconditioner (the paper's "simple preconditioner", Section II-B). */
+/* ------------------------------- learned element-interior preconditioner --
+ * Not in the paper, which uses a "simple preconditioner" (Section II-B,
+ * read as Jacobi).  The learned operator keeps Jacobi on every node except
+ * each element's learned nodes S: its interior nodes (1 <= i,j,k <= N-2)
+ * with a single copy, off the Dirichlet set.  On them
+ *     z_S = (1/gd_e) L^T diag(gamma_e) L r_S,  gamma_e = softplus(f(g_e)),
+ * with L an nI x nI matrix shared by all elements (nI = (N-2)^3, interior
+ * nodes in their own i-fastest order), f a 3-layer perceptron
+ * (6 -> n_hidden -> n_hidden -> nI, ReLU) on the element's six mean
+ * geometric factors divided by gd_e, the element mean of g1, g4, g6.
+ * L^T diag(gamma) L is symmetric positive semidefinite for any L, and the
+ * learned nodes of different elements are disjoint, so the operator is a
+ * fixed symmetric positive (semi)definite preconditioner that needs no
+ * exchange. */
+typedef struct nbx_lpi nbx_lpi;
+
+/* The model: L ([nIp][nIp] FP32, nIp = nI rounded up to 64, zero beyond nI)
+ * and the perceptron (an nbx_mlp arena with n_in 6, n_out nI), for training
+ * batches of up to max_batch rows (a multiple of 64; n_hidden a multiple of
+ * 64).  All parameters start at 0.  Allocates; synchronous.  NBX_EINVAL for
+ * N outside [3, 16] or other sizes. */
+int nbx_lpi_create(int N, int n_hidden, int max_batch, nbx_lpi **out);
+int nbx_lpi_destroy(nbx_lpi *m);
+/* nI, nIp and the length of the parameter arena [L | perceptron]. */
+int nbx_lpi_shape(nbx_lpi *m, int *nI, int *nIp, int64_t *n_params);
+/* Copies a parameter arena (device FP32) in, refreshes the BF16 copies and
+ * resets the optimiser state / copies parameters and gradients out (device,
+ * either may be NULL).  Async. */
+int nbx_lpi_set_params(nbx_lpi *m, const float *params, void *stream);
+int nbx_lpi_get_params(nbx_lpi *m, float *params, float *grads, void *stream);
+/* Gradient of the mean squared error, over B rows (a multiple of 64, at
+ * most max_batch) and the nI outputs, of Z = ((X L^T) * gamma(F)) L against
+ * T: X [B][nIp] BF16, T [B][nIp] FP32, F [B][64] BF16 (six features, then
+ * zeros).  *loss (device, may be NULL) receives the loss.  BF16 operands,
+ * FP32 accumulation.  Async. */
+int nbx_lpi_grad(nbx_lpi *m, const void *X, const float *T, const void *F, int B, double *loss,
+                 void *stream);
+/* Sets every gain bias (the perceptron's last bias) so that a model whose
+ * L is the identity and whose last layer is zero is the least-squares
+ * scalar map of the B rows (X, T as for nbx_lpi_grad): gamma = s0 with
+ * s0 = <X, T> / <X, X> (sums over all entries; 1 if <X, T> <= 0).  The
+ * usual start of training.  Async. */
+int nbx_lpi_init_scale(nbx_lpi *m, const void *X, const float *T, int B, void *stream);
+/* nbx_lpi_grad, then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with
+ * learning rate lr on every FP32 master parameter.  Async. */
+int nbx_lpi_train_step(nbx_lpi *m, const void *X, const float *T, const void *F, int B,
+                       float lr, double *loss, void *stream);
+
 typedef struct nbx_lp nbx_lp;
 
-/* Binds a problem and a network (both must outlive the handle), computes
- * the per-element geometric features, allocates feature/output buffers.
- * NBX_EINVAL if the network's sizes do not match N.  Synchronous. */
-int nbx_lp_create(nbx_problem *p, nbx_mlp *mlp, nbx_lp **out, void *stream);
+/* Binds a problem and a model of the same N (both must outlive the
+ * handle): computes each element's features and gd, and gamma for every
+ * element from the model's current parameters.  Allocates; synchronous.
+ * NBX_EINVAL if the sizes do not match. */
+int nbx_lp_create(nbx_problem *p, nbx_lpi *m, nbx_lp **out, void *stream);
 int nbx_lp_destroy(nbx_lp *lp);
+/* Recomputes gamma after the model's parameters changed.  Synchronous. */
+int nbx_lp_refresh(nbx_lp *lp, void *stream);
 /* gfeat[E][8]: six normalised factors, gd, 0.  Async. */
 int nbx_lp_geom_features(nbx_lp *lp, float *gfeat, void *stream);
-/* z = M(r) (device FP64 vectors, r != z).  Async. */
+/* z = M r (device FP64 vectors, r != z).  Async. */
 int nbx_lp_apply(nbx_lp *lp, const double *r, double *z, void *stream);
-/* Training rows from an FP64 CG state: for the nsel elements in elems
- * (device int32), X[row][in_pad] (BF16 features as above) and
- * T[row][out_pad] = ((xstar - x) - dinv r) / s_e on the element's nodes,
- * 0 elsewhere.  An index outside [0, E) yields an all-zero row.  Async. */
-int nbx_lp_samples(nbx_lp *lp, const double *r, const double *xstar, const double *x,
-                   const int32_t *elems, int nsel, void *X, float *T, void *stream);
+/* Training rows from the vector v - v0 (device FP64, [E][N^3]; v0 may be
+ * NULL for v alone) that the FP64 solver produced, an error x* - x_k or a
+ * residual r_k: for the nsel elements in elems (device int32), with
+ * s = |v_S| and y_S = A_SS v_S (the element operator on v with every node
+ * outside S set to zero, read on S):  X[row] = bf16(y_S / (s gd)),
+ * T[row] = v_S / s (0 beyond S and nI), F[row] = bf16 features.  A model
+ * with L^T diag(gamma) L = gd A_SS^-1 fits such rows exactly.  An index
+ * outside [0, E) or v_S = 0 gives an all-zero row.  Allocates two work
+ * vectors on the first call; async after that. */
+int nbx_lp_samples(nbx_lp *lp, const double *v, const double *v0, const int32_t *elems,
+                   int nsel, void *X, float *T, void *F, void *stream);
 /* Copies the recurrence residual of the problem's last solve. Async. */
 int nbx_problem_residual(nbx_problem *p, double *r, void *stream);
 /* Flexible PCG (Notay 2000, one stored direction: beta = -<z', A p> / <p, A p>,
- * each new direction A-orthogonal to the last) with M from x = 0.  If
- * it breaks down or reaches opts->max_iter (pass the Jacobi-PCG iteration
- * count to enforce "no worse than Jacobi") without meeting rtol, Jacobi-PCG
- * finishes the solve from the current x (from x = 0 if the flexible
- * iteration diverged) and res->fell_back = 1; res->iters counts all
- * iterations, res->outer_iters those of the flexible phase.
- * Synchronous; returns like nbx_pcg. */
+ * each new direction A-orthogonal to the last; the BF16 products make M
+ * linear only to rounding) from x = 0, for at most opts->max_iter
+ * iterations.  If it breaks down (<r, M r> or <p, A p> not positive),
+ * Jacobi-PCG continues from the current x (from x = 0 if the flexible
+ * iterate diverged) for the iterations the budget has left, and
+ * res->fell_back = 1; res->iters counts all iterations, res->outer_iters
+ * those of the flexible phase.  Synchronous; returns like nbx_pcg. */
 int nbx_pcg_learned(nbx_lp *lp, const double *b, double *x, const nbx_pcg_opts *opts,
                     nbx_pcg_result *res, void *stream);
 

@@ -227,3 +227,41 @@ def exact_params(shape: Shape, A_ref: np.ndarray, gd_ref: float):
     h = shape.n_hid
     return shape.pack([V.T, np.zeros((h, 6)), np.zeros(h), np.zeros((h, h)), np.zeros(h),
                        np.zeros((shape.K, h)), softplus_inv(lam)])
+
+
+def loss_and_grad_bf16(shape: Shape, params, X, T, F):
+    """loss_and_grad with the library's bfloat16 operand roundings: the
+    products take X, F, L, the perceptron's weights and hidden activations,
+    Q = Hx * gamma, the output gradient dZ, gamma * Pm and the perceptron's
+    back-propagated gradients rounded to bfloat16 (FP64 accumulation here,
+    FP32 in the library); bias gradients sum the unrounded dA and the
+    rounded hidden gradients, as the library's column sums do."""
+    r = bf16_round
+    L, W1, b1, W2, b2, W3, b3 = shape.unpack(params)
+    Xr, Fr, Lr = r(X), r(F), r(L)
+    W1r, W2r, W3r = r(W1), r(W2), r(W3)
+    T = np.asarray(T, dtype=np.float64)
+    B, n = Xr.shape[0], shape.nI
+    H1 = r(_relu(Fr @ W1r.T + b1))
+    H2 = r(_relu(H1 @ W2r.T + b2))
+    A = H2 @ W3r.T + b3
+    gamma = softplus(A)
+    Hx = Xr @ Lr.T
+    Q = r(Hx * gamma)
+    Z = Q @ Lr
+    Dl = Z - T
+    loss = float(np.sum(Dl ** 2) / (B * n))
+    dZ = r(2.0 * Dl / (B * n))
+    Pm = dZ @ Lr.T
+    dL = Q.T @ dZ + r(gamma * Pm).T @ Xr
+    dA = Hx * Pm * sigmoid(A)
+    dAr = r(dA)
+    dW3 = dAr.T @ H2
+    db3 = dA.sum(axis=0)
+    dH2 = r((dAr @ W3r) * (H2 > 0))
+    dW2 = dH2.T @ H1
+    db2 = dH2.sum(axis=0)
+    dH1 = r((dH2 @ W2r) * (H1 > 0))
+    dW1 = dH1.T @ Fr
+    db1 = dH1.sum(axis=0)
+    return loss, shape.pack([dL, dW1, db1, dW2, db2, dW3, db3])

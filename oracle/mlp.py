@@ -1,5 +1,5 @@
-"""FP64 reference for the element-local network of the learned
-preconditioner and for flexible PCG.
+"""FP64 reference for the 3-layer perceptron of the learned preconditioner
+(oracle/lpi.py builds the preconditioner on it) and for flexible PCG.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  The network is not in
 the paper; this follows the textbook definitions: a 3-layer perceptron
@@ -163,44 +163,3 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10, on_step=Non
         beta = -dot(z, w) / pw
         p = z + beta * p
     return x, max_iter, np.array(hist)
-
-
-# -------------------------------------------- learned preconditioner (FP64)
-
-def element_features(Gmat, N: int):
-    """Per element: the six element-mean factors divided by gd, the mean of
-    the three diagonal factors over the element, and gd itself."""
-    G = np.asarray(Gmat).reshape(-1, 6, N ** 3)
-    means = G.mean(axis=2)                       # [E][6]
-    gd = (means[:, 0] + means[:, 3] + means[:, 5]) / 3.0
-    return means / gd[:, None], gd
-
-
-def features(r, gfeat, gd, N: int, in_pad: int):
-    """Network input per element: r_e / ||r_e|| (N^3 values), the six
-    normalised factors, zeros to in_pad; and the output scale
-    s_e = ||r_e|| / gd_e."""
-    R = np.asarray(r).reshape(-1, N ** 3)
-    nrm = np.sqrt(np.sum(R ** 2, axis=1))
-    safe = np.where(nrm > 0, nrm, 1.0)
-    X = np.zeros((R.shape[0], in_pad))
-    X[:, :N ** 3] = np.where(nrm[:, None] > 0, R / safe[:, None], 0.0)
-    X[:, N ** 3:N ** 3 + 6] = gfeat
-    return X, nrm / gd
-
-
-def apply_learned(P, shape: Shape, params, r, gfeat, gd, round_inputs=False):
-    """z = dinv r + mask(dssum(c * s_e * f(x_e))) in FP64.  With
-    round_inputs the network inputs and weights are rounded to bfloat16
-    first (the GPU's operands)."""
-    from . import mask
-    N = P.N
-    X, s = features(r, gfeat, gd, N, shape.in_pad)
-    prm = params
-    if round_inputs:
-        X = bf16_round(X)
-        W1, b1, W2, b2, W3, b3 = shape.unpack(params)
-        prm = shape.pack([bf16_round(W1), b1, bf16_round(W2), b2, bf16_round(W3), b3])
-    _, _, Y = forward(shape, prm, X)
-    zl = (P.c.reshape(-1, N ** 3) * s[:, None] * Y[:, :N ** 3]).reshape(-1)
-    return P.dinv * r + mask(P.bnd, P.gs.dssum(zl))

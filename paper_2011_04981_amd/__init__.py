@@ -72,6 +72,8 @@ def lib():
         "nbx_brick_ids": ([i32, i32, i32, i32, vp, vp], i32),
         "nbx_ax": ([i32, vp, vp, vp, i32, i64, vp, vp], i32),
         "nbx_ax_tiled": ([i32, vp, vp, vp, i32, i64, vp, i32, vp], i32),
+        "nbx_ax_paired": ([i32, vp, vp, vp, i32, i64, vp, vp], i32),
+        "nbx_ax_paired_tiled": ([i32, vp, vp, vp, i32, i64, vp, i32, vp], i32),
         "nbx_ax_set_tile": ([i32, i32, i32], i32),
         "nbx_ax_get_tile": ([i32, i32], i32),
         "nbx_pcg_set_tile": ([i32, i32, i32], i32),
@@ -145,7 +147,9 @@ def _torch():
 
 
 def _dptr(t, dtype=None, name="tensor"):
-    """Device pointer of a contiguous CUDA tensor (checked)."""
+    """Device pointer of a contiguous, 16-byte aligned CUDA tensor (checked:
+    the kernels read and write 16-byte vectors, so a view at another offset
+    is refused)."""
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
@@ -153,6 +157,8 @@ def _dptr(t, dtype=None, name="tensor"):
         raise ValueError(f"{name} must be contiguous")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.data_ptr() % 16:
+        raise ValueError(f"{name} must start at a 16-byte aligned address")
     return C.c_void_p(t.data_ptr())
 
 
@@ -219,12 +225,12 @@ def deriv_device(N: int, device="cuda"):
 
 def geom_brick(ex: int, ey: int, ez: int, N: int, deform=None, with_xyz=False,
                device="cuda", stream=None):
-    """(G [E,3,N^3,2] planes of factor pairs, bm [E,N^3], xyz [3,E,N^3] or
+    """(G [E,6,N^3] one plane per factor, bm [E,N^3], xyz [3,E,N^3] or
     None) for a deformed brick, computed on the device."""
     torch = _torch()
     E = ex * ey * ez
     N3 = N ** 3
-    G = torch.empty((E, 3, N3, 2), dtype=torch.float64, device=device)
+    G = torch.empty((E, 6, N3), dtype=torch.float64, device=device)
     bm = torch.empty((E, N3), dtype=torch.float64, device=device)
     xyz = torch.empty((3, E, N3), dtype=torch.float64, device=device) if with_xyz else None
     d = np.ascontiguousarray(deform if deform is not None else
@@ -240,20 +246,20 @@ def geom(xyz, N: int, stream=None):
     if xyz.dim() != 3 or xyz.shape[0] != 3 or xyz.shape[2] != N ** 3:
         raise ValueError("xyz must be [3, E, N^3]")
     E = xyz.shape[1]
-    G = torch.empty((E, 3, N ** 3, 2), dtype=torch.float64, device=xyz.device)
+    G = torch.empty((E, 6, N ** 3), dtype=torch.float64, device=xyz.device)
     bm = torch.empty((E, N ** 3), dtype=torch.float64, device=xyz.device)
     _check(lib().nbx_geom(_dptr(xyz, torch.float64, "xyz"), N, E, _dptr(G), _dptr(bm),
                           _stream(stream)), "nbx_geom")
     return G, bm
 
 
-def _factor_layout(fn: str, src, N: int, out, stream):
+def _factor_layout(fn: str, src, N: int, out, stream, shape):
     torch = _torch()
     n6 = src.numel()
     if n6 % (6 * N ** 3):
         raise ValueError("the factors must hold 6 values for every node of whole elements")
     E = n6 // (6 * N ** 3)
-    out = torch.empty((E, 3, N ** 3, 2), dtype=torch.float64, device=src.device) \
+    out = torch.empty((E, *shape), dtype=torch.float64, device=src.device) \
         if out is None else _need(out, n6, "out")
     _check(getattr(lib(), fn)(_dptr(src, torch.float64, "factors"),
                               _dptr(out, torch.float64, "out"), N, E, _stream(stream)), fn)
@@ -263,16 +269,16 @@ def _factor_layout(fn: str, src, N: int, out, stream):
 def repack_g_aos_to_soa(g_aos, N: int, out=None, stream=None):
     """Geometric factors in the layout of the operator's g argument,
     g(6, N^3, E) with the factor fastest (a float64 tensor of E*N^3*6 values,
-    e.g. shaped [E, N^3, 6]), repacked on the device into the library's
-    planes of factor pairs [E, 3, N^3, 2]."""
-    return _factor_layout("nbx_repack_g_aos_to_soa", g_aos, N, out, stream)
+    e.g. shaped [E, N^3, 6]), repacked on the device into one plane per
+    factor, [E, 6, N^3], the layout every call takes."""
+    return _factor_layout("nbx_repack_g_aos_to_soa", g_aos, N, out, stream, (6, N ** 3))
 
 
 def pair_factors(g6, N: int, out=None, stream=None):
     """Geometric factors as one plane per factor, [E, 6, N^3] float64,
-    repacked on the device into the library's planes of factor pairs
-    [E, 3, N^3, 2] (nbx_pair_factors)."""
-    return _factor_layout("nbx_pair_factors", g6, N, out, stream)
+    repacked on the device into planes of factor pairs [E, 3, N^3, 2], the
+    layout of ax_paired (nbx_pair_factors)."""
+    return _factor_layout("nbx_pair_factors", g6, N, out, stream, (3, N ** 3, 2))
 
 
 def brick_ids(ex: int, ey: int, ez: int, N: int):
@@ -284,10 +290,7 @@ def brick_ids(ex: int, ey: int, ez: int, N: int):
 
 # --------------------------------------------------------------------- AX
 
-def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[int] = None):
-    """w = AX(u) for u [E, N^3] (float64 or float32), G [E, 3, N^3, 2]
-    (planes of factor pairs) of the same dtype, D [N, N] float64 (device).  epb forces a tile (elements per
-    workgroup); by default the library's tile table decides."""
+def _ax_call(fn, fn_tiled, u, G, D, N, out, stream, epb, gshape):
     torch = _torch()
     N = D.shape[0] if N is None else N
     E = u.numel() // N ** 3
@@ -298,28 +301,45 @@ def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[in
         raise TypeError(f"unsupported dtype {u.dtype}")
     if G.dtype != u.dtype:
         raise TypeError("G and u must share a dtype")
-    if G.numel() != 6 * u.numel():
-        raise ValueError("G must hold 6 factors per node")
+    if tuple(G.shape) != (E, *gshape(N)):
+        raise ValueError(f"G must be shaped {(E, *gshape(N))}, got {tuple(G.shape)}")
     w = torch.empty_like(u) if out is None else _need(out, u.numel(), "out")
+    args = (prec, _dptr(u, name="u"), _dptr(G, name="G"), _dptr(D, torch.float64, "D"), N, E,
+            _dptr(w, u.dtype, "w"))
     if epb is None:
-        _check(lib().nbx_ax(prec, _dptr(u, name="u"), _dptr(G, name="G"),
-                            _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
-                            _stream(stream)), "nbx_ax")
+        _check(getattr(lib(), fn)(*args, _stream(stream)), fn)
     else:
-        _check(lib().nbx_ax_tiled(prec, _dptr(u, name="u"), _dptr(G, name="G"),
-                                  _dptr(D, torch.float64, "D"), N, E, _dptr(w, u.dtype, "w"),
-                                  int(epb), _stream(stream)), "nbx_ax_tiled")
+        _check(getattr(lib(), fn_tiled)(*args, int(epb), _stream(stream)), fn_tiled)
     return w
 
 
+def ax(u, G, D, N: Optional[int] = None, out=None, stream=None, epb: Optional[int] = None):
+    """w = AX(u) (nbx_ax) for u [E, N^3] (float64 or float32), G [E, 6, N^3]
+    (one plane per factor) of the same dtype, D [N, N] float64 (device).
+    epb forces a tile (elements per workgroup); by default the library's
+    tile table decides."""
+    return _ax_call("nbx_ax", "nbx_ax_tiled", u, G, D, N, out, stream, epb,
+                    lambda N: (6, N ** 3))
+
+
+def ax_paired(u, Gp, D, N: Optional[int] = None, out=None, stream=None,
+              epb: Optional[int] = None):
+    """The same operator on factor pairs Gp [E, 3, N^3, 2] (pair_factors'
+    output; nbx_ax_paired)."""
+    return _ax_call("nbx_ax_paired", "nbx_ax_paired_tiled", u, Gp, D, N, out, stream, epb,
+                    lambda N: (3, N ** 3, 2))
+
+
 def g16_pack(G, N: int, gprec: int, stream=None):
-    """(G16 [E, 3, N^3, 2] int16 words, gscale [E] float32): the factors in
+    """From G [E, 6, N^3] float64: (G16 [E, 3, N^3, 2] int16 words, gscale
+    [E] float32), the factors in
     16-bit storage (gprec F16 or BF16) with per-element power-of-two
     scales, as factor pairs (g1,g2), (g3,g4), (g5,g6) per node
     (nbx_g16_pack)."""
     torch = _torch()
-    E = G.numel() // (6 * N ** 3)
-    _need(G, 6 * E * N ** 3, "G")
+    E = G.shape[0]
+    if tuple(G.shape) != (E, 6, N ** 3):
+        raise ValueError(f"G must be shaped (E, 6, {N ** 3})")
     G16 = torch.empty((E, 3, N ** 3, 2), dtype=torch.int16, device=G.device)
     gs = torch.empty(E, dtype=torch.float32, device=G.device)
     _check(lib().nbx_g16_pack(gprec, _dptr(G, torch.float64, "G"), N, E, _dptr(G16),
@@ -411,7 +431,8 @@ class GS:
 def jacobi_setup(G, D, gs: GS, N: int, stream=None):
     torch = _torch()
     E = G.shape[0]
-    _need(G, 6 * E * N ** 3, "G")
+    if tuple(G.shape) != (E, 6, N ** 3):
+        raise ValueError(f"G must be shaped (E, 6, {N ** 3})")
     _need(D, N * N, "D")
     if gs.n != E * N ** 3:
         raise ValueError("the gather-scatter plan does not match G")
@@ -466,14 +487,17 @@ class SolveResult:
 
 
 class Problem:
-    """Binds (G, D, N, E, gs); owns dinv and the solver workspace."""
+    """Binds (D, N, E, gs) and a copy of G [E, 6, N^3]; owns dinv and the
+    solver workspace."""
 
     def __init__(self, G, D, N: int, gs: GS, stream=None):
         torch = _torch()
-        self.G, self.D, self.N, self.gs = G, D, N, gs
+        self.D, self.N, self.gs = D, N, gs
         self.E = G.shape[0]
         self.n = self.E * N ** 3
-        _need(G, 6 * self.n, "G")
+        self.device = G.device
+        if tuple(G.shape) != (self.E, 6, N ** 3):
+            raise ValueError(f"G must be shaped (E, 6, {N ** 3})")
         _need(D, N * N, "D")
         if gs.n != self.n:
             raise ValueError("the gather-scatter plan does not match G")
@@ -496,7 +520,7 @@ class Problem:
 
     def dinv(self, stream=None):
         torch = _torch()
-        out = torch.empty((self.E, self.N ** 3), dtype=torch.float64, device=self.G.device)
+        out = torch.empty((self.E, self.N ** 3), dtype=torch.float64, device=self.device)
         _check(lib().nbx_problem_dinv(self._h, _dptr(out), _stream(stream)), "nbx_problem_dinv")
         return out
 
@@ -692,28 +716,134 @@ class Mlp:
         return loss
 
 
-class LearnedPrecond:
-    """Learned element-local preconditioner bound to a problem and a network
-    (nbx_lp_*): apply, training samples, flexible PCG with Jacobi fallback."""
+_LP_SIGS = {
+    "nbx_lpi_create": ([C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "nbx_lpi_destroy": ([C.c_void_p], C.c_int),
+    "nbx_lpi_shape": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                       C.POINTER(C.c_int64)], C.c_int),
+    "nbx_lpi_set_params": ([C.c_void_p] * 3, C.c_int),
+    "nbx_lpi_get_params": ([C.c_void_p] * 4, C.c_int),
+    "nbx_lpi_grad": ([C.c_void_p] * 4 + [C.c_int] + [C.c_void_p] * 2, C.c_int),
+    "nbx_lpi_train_step": ([C.c_void_p] * 4 + [C.c_int, C.c_float] + [C.c_void_p] * 2, C.c_int),
+    "nbx_lp_create": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p], C.c_int),
+    "nbx_lp_destroy": ([C.c_void_p], C.c_int),
+    "nbx_lp_refresh": ([C.c_void_p] * 2, C.c_int),
+    "nbx_lp_geom_features": ([C.c_void_p] * 3, C.c_int),
+    "nbx_lp_apply": ([C.c_void_p] * 4, C.c_int),
+    "nbx_lp_samples": ([C.c_void_p] * 4 + [C.c_int] + [C.c_void_p] * 4, C.c_int),
+    "nbx_lpi_init_scale": ([C.c_void_p] * 3 + [C.c_int, C.c_void_p], C.c_int),
+    "nbx_problem_residual": ([C.c_void_p] * 3, C.c_int),
+    "nbx_pcg_learned": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PcgOpts),
+                         C.POINTER(PcgResult), C.c_void_p], C.c_int),
+}
 
-    def __init__(self, problem: "Problem", net: Mlp, stream=None):
-        L = lib()
-        for name, args in {"nbx_lp_create": [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
-                                             C.c_void_p],
-                           "nbx_lp_destroy": [C.c_void_p],
-                           "nbx_lp_geom_features": [C.c_void_p, C.c_void_p, C.c_void_p],
-                           "nbx_lp_apply": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
-                           "nbx_lp_samples": [C.c_void_p] * 5 + [C.c_int] + [C.c_void_p] * 3,
-                           "nbx_problem_residual": [C.c_void_p] * 3,
-                           "nbx_pcg_learned": [C.c_void_p, C.c_void_p, C.c_void_p,
-                                               C.POINTER(PcgOpts), C.POINTER(PcgResult),
-                                               C.c_void_p]}.items():
+
+def _lp_lib():
+    L = lib()
+    if not getattr(L, "_lp_sigs", False):
+        for name, (args, res) in _LP_SIGS.items():
             getattr(L, name).argtypes = args
-            getattr(L, name).restype = C.c_int
+            getattr(L, name).restype = res
+        L._lp_sigs = True
+    return L
+
+
+FEAT = 64   # width of a feature row (six features, then zeros)
+
+
+class InteriorModel:
+    """The learned element-interior preconditioner's model (nbx_lpi_*): L
+    and the gains perceptron, with the training step."""
+
+    def __init__(self, N: int, n_hidden: int = 128, max_batch: int = 1024):
+        L = _lp_lib()
         h = C.c_void_p()
-        _check(L.nbx_lp_create(problem._h, net.handle, C.byref(h), _stream(stream)),
+        _check(L.nbx_lpi_create(N, n_hidden, max_batch, C.byref(h)), "nbx_lpi_create")
+        self._h = h
+        ni, nip, npar = C.c_int(), C.c_int(), C.c_int64()
+        _check(L.nbx_lpi_shape(h, C.byref(ni), C.byref(nip), C.byref(npar)), "nbx_lpi_shape")
+        self.N, self.n_hidden, self.max_batch = N, n_hidden, max_batch
+        self.nI, self.nIp, self.n_params = ni.value, nip.value, npar.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbx_lpi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        torch = _torch()
+        _need(params, self.n_params, "params")
+        _check(_lp_lib().nbx_lpi_set_params(self._h, _dptr(params, torch.float32),
+                                            _stream(stream)), "nbx_lpi_set_params")
+
+    def get_params(self, grads=False, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        p, g = (None, _dptr(out)) if grads else (_dptr(out), None)
+        _check(_lp_lib().nbx_lpi_get_params(self._h, p, g, _stream(stream)),
+               "nbx_lpi_get_params")
+        return out
+
+    def _rows(self, X, T, F):
+        B = X.shape[0]
+        if X.dim() != 2 or X.shape[1] != self.nIp:
+            raise ValueError(f"X must be [B, {self.nIp}]")
+        if tuple(T.shape) != (B, self.nIp) or tuple(F.shape) != (B, FEAT):
+            raise ValueError(f"T must be [B, {self.nIp}] and F [B, {FEAT}]")
+        if B < 64 or B % 64 or B > self.max_batch:
+            raise ValueError(f"B must be a multiple of 64 up to {self.max_batch}")
+        return B
+
+    def init_scale(self, X, T, stream=None):
+        """Gain biases from the least-squares scalar fit of rows (X, T)
+        (nbx_lpi_init_scale)."""
+        torch = _torch()
+        if X.dim() != 2 or X.shape[1] != self.nIp or tuple(T.shape) != tuple(X.shape):
+            raise ValueError(f"X and T must be [B, {self.nIp}]")
+        _check(_lp_lib().nbx_lpi_init_scale(self._h, _dptr(X, torch.bfloat16),
+                                            _dptr(T, torch.float32), X.shape[0],
+                                            _stream(stream)), "nbx_lpi_init_scale")
+
+    def grad(self, X, T, F, stream=None):
+        torch = _torch()
+        B = self._rows(X, T, F)
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+        _check(_lp_lib().nbx_lpi_grad(self._h, _dptr(X, torch.bfloat16),
+                                      _dptr(T, torch.float32), _dptr(F, torch.bfloat16), B,
+                                      _dptr(loss), _stream(stream)), "nbx_lpi_grad")
+        return loss
+
+    def train_step(self, X, T, F, lr: float, stream=None):
+        torch = _torch()
+        B = self._rows(X, T, F)
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+        _check(_lp_lib().nbx_lpi_train_step(self._h, _dptr(X, torch.bfloat16),
+                                            _dptr(T, torch.float32), _dptr(F, torch.bfloat16),
+                                            B, float(lr), _dptr(loss), _stream(stream)),
+               "nbx_lpi_train_step")
+        return loss
+
+
+class LearnedPrecond:
+    """The learned element-interior preconditioner bound to a problem and a
+    model (nbx_lp_*): apply, training rows, flexible PCG with the Jacobi
+    fallback."""
+
+    def __init__(self, problem: "Problem", model: InteriorModel, stream=None):
+        h = C.c_void_p()
+        _check(_lp_lib().nbx_lp_create(problem._h, model.handle, C.byref(h), _stream(stream)),
                "nbx_lp_create")
-        self._h, self.problem, self.net = h, problem, net
+        self._h, self.problem, self.model = h, problem, model
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -726,10 +856,14 @@ class LearnedPrecond:
         except Exception:
             pass
 
+    def refresh(self, stream=None):
+        """Recomputes the per-element gains after the model changed."""
+        _check(_lp_lib().nbx_lp_refresh(self._h, _stream(stream)), "nbx_lp_refresh")
+
     def geom_features(self, stream=None):
         torch = _torch()
         g = torch.empty((self.problem.E, 8), dtype=torch.float32, device="cuda")
-        _check(lib().nbx_lp_geom_features(self._h, _dptr(g), _stream(stream)),
+        _check(_lp_lib().nbx_lp_geom_features(self._h, _dptr(g), _stream(stream)),
                "nbx_lp_geom_features")
         return g
 
@@ -737,30 +871,36 @@ class LearnedPrecond:
         torch = _torch()
         _need(r, self.problem.n, "r")
         z = torch.empty_like(r)
-        _check(lib().nbx_lp_apply(self._h, _dptr(r, torch.float64), _dptr(z), _stream(stream)),
-               "nbx_lp_apply")
+        _check(_lp_lib().nbx_lp_apply(self._h, _dptr(r, torch.float64), _dptr(z),
+                                      _stream(stream)), "nbx_lp_apply")
         return z
 
-    def samples(self, r, xstar, x, elems, stream=None):
-        """(X [n, in_pad] bf16, T [n, out_pad] f32) for the element indices."""
+    def samples(self, v, elems, v0=None, stream=None):
+        """(X [n, nIp] bf16, T [n, nIp] f32, F [n, 64] bf16) rows from the
+        solver vector v - v0 (v alone if v0 is None) for the element indices
+        elems (int32, device)."""
         torch = _torch()
-        for t, nm in ((r, "r"), (xstar, "xstar"), (x, "x")):
-            _need(t, self.problem.n, nm)
+        _need(v, self.problem.n, "v")
+        if v0 is not None:
+            _need(v0, self.problem.n, "v0")
         n = elems.numel()
-        X = torch.empty((n, self.net.in_pad), dtype=torch.bfloat16, device="cuda")
-        T = torch.empty((n, self.net.out_pad), dtype=torch.float32, device="cuda")
-        _check(lib().nbx_lp_samples(self._h, _dptr(r, torch.float64),
-                                    _dptr(xstar, torch.float64), _dptr(x, torch.float64),
-                                    _dptr(elems, torch.int32), n, _dptr(X), _dptr(T),
-                                    _stream(stream)), "nbx_lp_samples")
-        return X, T
+        nIp = self.model.nIp
+        X = torch.empty((n, nIp), dtype=torch.bfloat16, device="cuda")
+        T = torch.empty((n, nIp), dtype=torch.float32, device="cuda")
+        F = torch.empty((n, FEAT), dtype=torch.bfloat16, device="cuda")
+        _check(_lp_lib().nbx_lp_samples(self._h, _dptr(v, torch.float64),
+                                        _dptr(v0, torch.float64, "v0") if v0 is not None
+                                        else None,
+                                        _dptr(elems, torch.int32), n, _dptr(X), _dptr(T),
+                                        _dptr(F), _stream(stream)), "nbx_lp_samples")
+        return X, T, F
 
     def residual(self, stream=None):
         """The recurrence residual left by the problem's last solve."""
         torch = _torch()
         r = torch.empty((self.problem.E, self.problem.N ** 3), dtype=torch.float64,
                         device="cuda")
-        _check(lib().nbx_problem_residual(self.problem._h, _dptr(r), _stream(stream)),
+        _check(_lp_lib().nbx_problem_residual(self.problem._h, _dptr(r), _stream(stream)),
                "nbx_problem_residual")
         return r
 
@@ -770,8 +910,9 @@ class LearnedPrecond:
         x = torch.empty_like(b) if x is None else _need(x, self.problem.n, "x")
         o = default_opts(**opts)
         r = PcgResult()
-        st = lib().nbx_pcg_learned(self._h, _dptr(b, torch.float64), _dptr(x, torch.float64),
-                                   C.byref(o), C.byref(r), _stream(stream))
+        st = _lp_lib().nbx_pcg_learned(self._h, _dptr(b, torch.float64),
+                                       _dptr(x, torch.float64), C.byref(o), C.byref(r),
+                                       _stream(stream))
         if st < 0 and st != -5:
             raise NbxError(st, "nbx_pcg_learned")
         return x, SolveResult(st, r.iters, r.outer_iters, r.relres, r.true_relres,

@@ -45,7 +45,7 @@ def time_tiles(prec: int, N: int, nodes: int = 16_000_000, reps: int = 20,
     E = max(64, nodes // N ** 3)
     g = torch.Generator(device="cuda").manual_seed(seed)
     u = torch.rand((E, N ** 3), dtype=dtype, device="cuda", generator=g)
-    G = torch.rand((E, 3, N ** 3, 2), dtype=torch.float64 if prec == F16 else dtype,
+    G = torch.rand((E, 6, N ** 3), dtype=torch.float64 if prec == F16 else dtype,
                    device="cuda", generator=g)
     w = torch.empty_like(u)
     from . import deriv_device

@@ -13,6 +13,10 @@ int ax_launch_f64_tiled(int N, int epb, const double *u, const double *G, const 
                         double *w, int64_t E, hipStream_t s);
 int ax_launch_f32_tiled(int N, int epb, const float *u, const float *G, const double *D,
                         float *w, int64_t E, hipStream_t s);
+int ax_launch_f64_planes_tiled(int N, int epb, const double *u, const double *G,
+                               const double *D, double *w, int64_t E, hipStream_t s);
+int ax_launch_f32_planes_tiled(int N, int epb, const float *u, const float *G, const double *D,
+                               float *w, int64_t E, hipStream_t s);
 int ax_pcg_launch_f64_tiled(int N, int epb, const double *G, const double *D, int64_t E,
                             const double *z, double *p, double *w, double *part,
                             const double *scal, hipStream_t s);
@@ -141,15 +145,33 @@ static int ax_check(int prec, const void *u, const void *G, const double *D, int
     return 1;   // proceed
 }
 
+// The C ABI's operator: G in one plane per factor, [E][6][N^3].
+static int ax_planes(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
+                     void *w, int epb, hipStream_t s)
+{
+    if (prec == NBX_F64)
+        return ax_launch_f64_planes_tiled(N, epb, (const double *)u, (const double *)G, D,
+                                          (double *)w, E, s);
+    return ax_launch_f32_planes_tiled(N, epb, (const float *)u, (const float *)G, D,
+                                      (float *)w, E, s);
+}
+
+// The same operator on factor pairs, [E][3][N^3][2] (the solvers' layout).
+static int ax_pairs(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
+                    void *w, int epb, hipStream_t s)
+{
+    if (prec == NBX_F64)
+        return ax_launch_f64_tiled(N, epb, (const double *)u, (const double *)G, D, (double *)w,
+                                   E, s);
+    return ax_launch_f32_tiled(N, epb, (const float *)u, (const float *)G, D, (float *)w, E, s);
+}
+
 extern "C" int nbx_ax(int prec, const void *u, const void *G, const double *D, int N,
                       int64_t E, void *w, void *stream)
 {
     const int c = ax_check(prec, u, G, D, N, E, w);
     if (c != 1) return c;
-    hipStream_t s = as_stream(stream);
-    if (prec == NBX_F64)
-        return ax_launch_f64((const double *)u, (const double *)G, D, N, E, (double *)w, s);
-    return ax_launch_f32((const float *)u, (const float *)G, D, N, E, (float *)w, s);
+    return ax_planes(prec, u, G, D, N, E, w, ax_tile(prec, N), as_stream(stream));
 }
 
 extern "C" int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N,
@@ -158,11 +180,24 @@ extern "C" int nbx_ax_tiled(int prec, const void *u, const void *G, const double
     if (!valid_epb(epb)) return NBX_EINVAL;
     const int c = ax_check(prec, u, G, D, N, E, w);
     if (c != 1) return c;
-    hipStream_t s = as_stream(stream);
-    if (prec == NBX_F64)
-        return ax_launch_f64_tiled(N, epb, (const double *)u, (const double *)G, D,
-                                   (double *)w, E, s);
-    return ax_launch_f32_tiled(N, epb, (const float *)u, (const float *)G, D, (float *)w, E, s);
+    return ax_planes(prec, u, G, D, N, E, w, epb, as_stream(stream));
+}
+
+extern "C" int nbx_ax_paired(int prec, const void *u, const void *Gp, const double *D, int N,
+                             int64_t E, void *w, void *stream)
+{
+    const int c = ax_check(prec, u, Gp, D, N, E, w);
+    if (c != 1) return c;
+    return ax_pairs(prec, u, Gp, D, N, E, w, ax_tile(prec, N), as_stream(stream));
+}
+
+extern "C" int nbx_ax_paired_tiled(int prec, const void *u, const void *Gp, const double *D,
+                                   int N, int64_t E, void *w, int epb, void *stream)
+{
+    if (!valid_epb(epb)) return NBX_EINVAL;
+    const int c = ax_check(prec, u, Gp, D, N, E, w);
+    if (c != 1) return c;
+    return ax_pairs(prec, u, Gp, D, N, E, w, epb, as_stream(stream));
 }
 
 static int set_tile(int kind, int prec, int N, int epb)

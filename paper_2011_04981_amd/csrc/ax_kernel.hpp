@@ -109,6 +109,21 @@ __device__ inline void ax_pair(const GT *Ge, int q, T &lo, T &hi)
     }
 }
 
+// Factors 2h and 2h+1 of node `node` of an element (Ge points at the
+// element's 6 N^3 values): one pair load from the pair planes, or (PL, the
+// C ABI's [E][6][N^3] layout) two loads from planes 2h and 2h+1.
+template <typename T, typename GT, bool PL, int N3>
+__device__ inline void ax_gpair(const GT *Ge, int h, int node, T &lo, T &hi)
+{
+    if constexpr (PL) {
+        static_assert(std::is_same<GT, T>::value, "planes hold T");
+        lo = __builtin_nontemporal_load(Ge + (2 * h) * N3 + node);
+        hi = __builtin_nontemporal_load(Ge + (2 * h + 1) * N3 + node);
+    } else {
+        ax_pair<T>(Ge, h * N3 + node, lo, hi);
+    }
+}
+
 template <typename T>
 __device__ inline void ax_st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 // Fused multiply-add written out: every instantiation (tile, fused or not)
@@ -123,13 +138,14 @@ __device__ inline float ax_fma(float a, float b, float c) { return __builtin_fma
 // blk selects the block's elements [blk*EPB, blk*EPB + EPB) of this
 // operator instance (blockIdx.x for a single operator; a table entry when
 // one launch serves several independent problems).
-// G is in planes of factor pairs (g_index).  GT is its storage type (T,
+// G is in planes of factor pairs (g_index), or with PL in one plane per
+// factor (gp_index, T storage only).  GT is its storage type (T,
 // or g_f16 / g_bf16 with T = float); for 16-bit storage G_e holds
 // G_e / gscale[e] (gscale[e] a power of two), each pair in one 32-bit word
 // (see ax_pair), and
 // the element's result is multiplied by gscale[e], which in FP32 is exact
 // and commutes with every rounding of the element's arithmetic.
-template <typename T, int N, int EPB, bool PCG, typename GT = T>
+template <typename T, int N, int EPB, bool PCG, typename GT = T, bool PL = false>
 __device__ __forceinline__ void
 ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__restrict__ Dg,
         T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
@@ -186,7 +202,8 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
 #pragma unroll
     for (int h = 0; h < 3; ++h)
 #pragma unroll
-        for (int k = 0; k < PF; ++k) ax_pair<T>(Ge, h * N3 + k * N2 + tc, g[2 * h][k], g[2 * h + 1][k]);
+        for (int k = 0; k < PF; ++k)
+            ax_gpair<T, GT, PL, N3>(Ge, h, k * N2 + tc, g[2 * h][k], g[2 * h + 1][k]);
     for (int q = t; q < N2; q += NT) s_D[q] = (T)Dg[q];
     if constexpr (PCG) {
         if (valid) {
@@ -238,9 +255,9 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
                 if constexpr ((sizeof(T) == sizeof(double) && N >= 11 && N != 15) ||
                               (sizeof(T) == sizeof(float) && N >= 13))
                     asm volatile("" : "+v"(off) : "v"(wt[k - 1]));
-                ax_pair<T>(Ge, off, g1, g2);
-                ax_pair<T>(Ge, off + N3, g3, g4);
-                ax_pair<T>(Ge, off + 2 * N3, g5, g6);
+                ax_gpair<T, GT, PL, N3>(Ge, 0, off, g1, g2);
+                ax_gpair<T, GT, PL, N3>(Ge, 1, off, g3, g4);
+                ax_gpair<T, GT, PL, N3>(Ge, 2, off, g5, g6);
             }
             const T wr = ax_fma(g3, ut, ax_fma(g2, us, g1 * ur));
             const T ws = ax_fma(g5, ut, ax_fma(g4, us, g2 * ur));
@@ -292,19 +309,20 @@ ax_body(const T *__restrict__ uin, const GT *__restrict__ G, const double *__res
     }
 }
 
-template <typename T, int N, int EPB, bool PCG, typename GT = T>
+template <typename T, int N, int EPB, bool PCG, typename GT = T, bool PL = false>
 __global__ void __launch_bounds__((AxShape<N, EPB>::NT))
 ax_kernel(const T *__restrict__ uin, const GT *__restrict__ G, const double *__restrict__ Dg,
           T *__restrict__ w, T *__restrict__ pio, double *__restrict__ part,
           const double *__restrict__ scal, int64_t E, const float *__restrict__ gscale)
 {
-    ax_body<T, N, EPB, PCG, GT>(uin, G, Dg, w, pio, part, scal, E, (int64_t)blockIdx.x, gscale);
+    ax_body<T, N, EPB, PCG, GT, PL>(uin, G, Dg, w, pio, part, scal, E, (int64_t)blockIdx.x,
+                                    gscale);
 }
 
 // Elements per workgroup the library may use (the autotuner's search space).
 constexpr int kEpbChoices[] = {1, 2, 4, 8};
 
-template <typename T, bool PCG, int N, typename GT = T>
+template <typename T, bool PCG, int N, typename GT = T, bool PL = false>
 int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p, double *part,
                   const double *scal, int64_t E, hipStream_t s, const float *gscale = nullptr)
 {
@@ -313,7 +331,8 @@ int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p,
         if constexpr (AxShape<N, EE>::template fits<T>()) {                                  \
             constexpr int NT_ = AxShape<N, EE>::NT;                                          \
             const int64_t nb = (E + EE - 1) / EE;                                            \
-            hipLaunchKernelGGL((ax_kernel<T, N, EE, PCG, GT>), dim3((unsigned)nb), dim3(NT_), \
+            hipLaunchKernelGGL((ax_kernel<T, N, EE, PCG, GT, PL>), dim3((unsigned)nb),    \
+                               dim3(NT_),                                              \
                                0, s, u, G, D, w, p, part, scal, E, gscale);                  \
             return NBX_OK;                                                                   \
         } else {                                                                             \
@@ -330,7 +349,7 @@ int ax_launch_epb(int epb, const T *u, const GT *G, const double *D, T *w, T *p,
 #undef NBX_EPB_CASE
 }
 
-template <typename T, bool PCG, typename GT = T>
+template <typename T, bool PCG, typename GT = T, bool PL = false>
 int ax_launch_any(int N, int epb, const T *u, const GT *G, const double *D, T *w, T *p,
                   double *part, const double *scal, int64_t E, hipStream_t s,
                   const float *gscale = nullptr)
@@ -340,7 +359,8 @@ int ax_launch_any(int N, int epb, const T *u, const GT *G, const double *D, T *w
     int st;
 #define NBX_N_CASE(NN)                                                                     \
     case NN:                                                                               \
-        st = ax_launch_epb<T, PCG, NN, GT>(epb, u, G, D, w, p, part, scal, E, s, gscale);  \
+        st = ax_launch_epb<T, PCG, NN, GT, PL>(epb, u, G, D, w, p, part, scal, E, s,       \
+                                               gscale);                                    \
         break;
     switch (N) {
         NBX_N_CASE(2) NBX_N_CASE(3) NBX_N_CASE(4) NBX_N_CASE(5) NBX_N_CASE(6)

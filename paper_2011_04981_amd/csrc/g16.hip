@@ -35,10 +35,11 @@ __device__ inline uint16_t to16(int bf16, double v)
     return bf16 ? f32_to_bf16_rne(f) : __builtin_bit_cast(uint16_t, (_Float16)f);
 }
 
-// one block per element: max |G_e|, the scale, then the packed words
+// one block per element: max |G_e|, the scale, then the packed words.
+// G is [E][6][N^3] (planes != 0, the C ABI's layout) or factor pairs.
 __global__ void __launch_bounds__(256)
-g16_pack_kernel(int bf16, int N3, const double *__restrict__ G, uint32_t *__restrict__ G16,
-                float *__restrict__ gscale)
+g16_pack_kernel(int bf16, int planes, int N3, const double *__restrict__ G,
+                uint32_t *__restrict__ G16, float *__restrict__ gscale)
 {
     const int n6 = 6 * N3;
     __shared__ double s_max[4];
@@ -57,13 +58,32 @@ g16_pack_kernel(int bf16, int N3, const double *__restrict__ G, uint32_t *__rest
     if (threadIdx.x == 0) gscale[e] = ldexpf(1.0f, ex);
     uint32_t *out = G16 + (size_t)e * 3 * N3;
     for (int q = threadIdx.x; q < 3 * N3; q += blockDim.x) {
-        const uint32_t lo = to16(bf16, Ge[2 * q] * inv);       // G's pair planes have
-        const uint32_t hi = to16(bf16, Ge[2 * q + 1] * inv);   // the words' order
+        // word q = h N^3 + node holds factors 2h (low half) and 2h + 1
+        const int h = q / N3, node = q - h * N3;
+        const double glo = planes ? Ge[(2 * h) * N3 + node] : Ge[2 * q];
+        const double ghi = planes ? Ge[(2 * h + 1) * N3 + node] : Ge[2 * q + 1];
+        const uint32_t lo = to16(bf16, glo * inv);
+        const uint32_t hi = to16(bf16, ghi * inv);
         out[q] = lo | (hi << 16);
     }
 }
 
 }  // namespace
+
+int g16_pack_launch(int gprec, int planes, const double *G, int N, int64_t E, void *G16,
+                    float *gscale, hipStream_t s)
+{
+    if (N < 2 || N > kMaxN || E < 0) return NBX_EINVAL;
+    if (gprec != NBX_F16 && gprec != NBX_BF16) return NBX_EUNSUPPORTED;
+    if (E == 0) return NBX_OK;
+    if (!G || !G16 || !gscale) return NBX_EINVAL;
+    if (E > 0x7fffffffLL) return NBX_EUNSUPPORTED;
+    hipLaunchKernelGGL(g16_pack_kernel, dim3((unsigned)E), dim3(256), 0, s,
+                       gprec == NBX_BF16 ? 1 : 0, planes, N * N * N, G, (uint32_t *)G16, gscale);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
 }  // namespace nbx
 
 using namespace nbx;
@@ -71,15 +91,7 @@ using namespace nbx;
 extern "C" int nbx_g16_pack(int gprec, const double *G, int N, int64_t E, void *G16,
                             float *gscale, void *stream)
 {
-    if (N < 2 || N > kMaxN || E < 0) return NBX_EINVAL;
-    if (gprec != NBX_F16 && gprec != NBX_BF16) return NBX_EUNSUPPORTED;
-    if (E == 0) return NBX_OK;
-    if (!G || !G16 || !gscale) return NBX_EINVAL;
-    if (E > 0x7fffffffLL) return NBX_EUNSUPPORTED;
-    hipLaunchKernelGGL(g16_pack_kernel, dim3((unsigned)E), dim3(256), 0, as_stream(stream),
-                       gprec == NBX_BF16 ? 1 : 0, N * N * N, G, (uint32_t *)G16, gscale);
-    NBX_LAUNCH_CHECK();
-    return NBX_OK;
+    return g16_pack_launch(gprec, 1, G, N, E, G16, gscale, as_stream(stream));
 }
 
 extern "C" int nbx_ax_g16(int gprec, const float *u, const void *G16, const float *gscale,

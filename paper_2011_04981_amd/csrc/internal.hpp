@@ -28,14 +28,22 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 constexpr int kMaxN = 16;
 
-// Geometric factors: per element three planes of factor pairs (g1,g2),
-// (g3,g4), (g5,g6), one pair per node, so that the operator fetches a pair
-// with one 16-byte (FP64) or 8-byte (FP32) load.  Factor f of node p of
-// element e:
+// Geometric factors.  Every G of the C ABI is [E][6][N^3], one plane per
+// factor (gp_index).  Inside a problem the library keeps its own copy in
+// three planes of factor pairs per element, (g1,g2), (g3,g4), (g5,g6), one
+// pair per node, so that the solvers' fused operator fetches a pair with
+// one 16-byte (FP64) or 8-byte (FP32) load (g_index); nbx_ax_paired takes
+// that layout too.  Factor f of node p of element e:
+__host__ __device__ inline int64_t gp_index(int64_t e, int f, int64_t p, int N3)
+{
+    return (e * 6 + f) * N3 + p;
+}
 __host__ __device__ inline int64_t g_index(int64_t e, int f, int64_t p, int N3)
 {
     return ((e * 3 + (f >> 1)) * N3 + p) * 2 + (f & 1);
 }
+// [E][6][N^3] planes to factor pairs (dst must not overlap src); async.
+int pair_factors_launch(const double *g6, double *g_pairs, int N, int64_t E, hipStream_t s);
 
 // GLL nodes / weights / derivative matrix computed on the host.
 int gll_host(int N, double *xi, double *w);
@@ -59,7 +67,7 @@ template <typename T>
 int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s,
                  const double *flag = nullptr);
 
-// AX launch (double / float).
+// AX launch (double / float) on factor pairs, the solvers' layout.
 int ax_launch_f64(const double *u, const double *G, const double *D, int N, int64_t E,
                   double *w, hipStream_t s);
 int ax_launch_f32(const float *u, const float *G, const double *D, int N, int64_t E,
@@ -78,6 +86,10 @@ int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscal
 int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const double *D, int N,
                       int64_t E, const float *z, float *p, float *w, double *part,
                       const double *scal, hipStream_t s);
+// Packs G (FP64, planes != 0: [E][6][N^3], else factor pairs) into the
+// 16-bit words and per-element scales of the reduced-storage operator.
+int g16_pack_launch(int gprec, int planes, const double *G, int N, int64_t E, void *G16,
+                    float *gscale, hipStream_t s);
 // Elements per workgroup currently selected for (prec, N): ax_tile for the
 // plain operator, pcg_tile for the fused first stage of the solvers; and
 // the resulting number of fused-stage workgroups (partials) for E elements.

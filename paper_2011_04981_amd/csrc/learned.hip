@@ -1,33 +1,55 @@
-// learned.hip -- an element-local learned preconditioner for the CG solve
-// and the flexible CG that uses it.
+// learned.hip -- the learned element-interior preconditioner bound to a
+// problem, its training rows, and the flexible CG that uses it.
 //
-// The paper's CG uses a "simple preconditioner" (Section II-B); this adds a
-// learned correction on top of Jacobi:
-//   M(r) = dinv r + mask(dssum(c * s_e * f(x_e)))
-// where, per element, x_e = [r_e / ||r_e||, the six element-mean geometric
-// factors / gd_e] (BF16), s_e = ||r_e|| / gd_e, gd_e the element mean of the
-// diagonal factors, and f the 3-layer network of mlp.hip (BF16 matrix-core
-// products, FP32 accumulation).  c = 1/multiplicity averages the element
-// outputs at shared nodes.  A network that outputs zero gives Jacobi back.
-// M is nonlinear, so the outer iteration is flexible PCG (Notay 2000, one
-// stored direction: beta = -<z_new, A p> / <p, A p> makes each new direction
-// A-orthogonal to the previous one).  Training pairs come from
-// the FP64 solver: T_e = (e_e - dinv r_e) / s_e with e = x* - x_k.
+// The paper's CG uses a "simple preconditioner" (Section II-B, read as
+// Jacobi).  The learned operator keeps Jacobi on every node except each
+// element's learned interior nodes S (interior, one copy, off the Dirichlet
+// set), where
+//     z_S = (1/gd_e) L^T diag(gamma_e) L r_S
+// with the model of lpi.hip: L shared by all elements, gamma_e from the
+// perceptron on the element's normalised mean factors, computed once per
+// binding.  The nodes in S belong to one element each, so the operator
+// needs no exchange and is symmetric positive definite: a fixed SPD
+// preconditioner.  Its BF16 products make it linear only to rounding, so
+// the solve is flexible CG (Notay 2000, one stored direction:
+// beta = -<z', A p> / <p, A p>), which tolerates that.
+//
+// Application per CG iteration: gather r_S into BF16 rows [E][nIp], one
+// GEMM X L^T with the gains multiplied in its epilogue (BF16 out), one GEMM
+// with L (FP32 out), and the kernel that forms z, <r, z>_c and <z, A p>_c.
+//
+// Training rows from a vector v the FP64 solver produced (an error x* - x,
+// formed here as the difference of two vectors, or a residual r):
+// X = A_SS v_S / (|v_S| gd_e), T = v_S / |v_S|, and the element's features;
+// A_SS v_S is AX of v with every node outside S set to zero, read on S.
 #include "solver.hpp"
 #include "solver_kernels.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <new>
 
 struct nbx_mlp;
+struct nbx_lpi;
 
 namespace nbx {
 
+int gemm_bf16(int ta, int tb, int epi, int M, int N, int K, const uint16_t *A, int lda,
+              const uint16_t *B, int ldb, float *C, int ldc, uint16_t *Cb, int ldcb,
+              const float *bias, const uint16_t *act, int ldact, hipStream_t s,
+              const float *mul);
 int mlp_forward_rows(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s);
-int mlp_dims(nbx_mlp *P, int *n_in, int *n_out, int *in_pad, int *out_pad, int *max_batch);
+int lpi_dims(const nbx_lpi *M, int *N, int *nI, int *nIp);
+const uint16_t *lpi_Lb(const nbx_lpi *M);
+nbx_mlp *lpi_mlp(const nbx_lpi *M);
+int lpi_max_batch(const nbx_lpi *M);
 
 namespace {
+
+constexpr int kEpiF32 = 0, kEpiMulBf16 = 5;   // GEMM epilogues of mlp.hip
+constexpr int kFeat = 64;                     // feature row width (six used)
+constexpr int64_t kGemmRows = 1 << 21;        // rows per GEMM launch (grid.y < 2^16)
 
 __device__ __forceinline__ uint16_t lp_f2bf(float f)
 {
@@ -48,9 +70,23 @@ __device__ inline double lp_block_sum(double v, double *s)
     return t;
 }
 
-// gfeat[e][0..5] = element means of the six factors / gd, gfeat[e][6] = gd.
+// Local node number of interior node q (the interior's own order, i fastest).
+__device__ __forceinline__ int lp_inode(int q, int N)
+{
+    const int m = N - 2;
+    const int i = 1 + q % m, j = 1 + (q / m) % m, k = 1 + q / (m * m);
+    return i + N * (j + N * k);
+}
+
+// A learned node: one copy and not Dirichlet (info = multiplicity | 0x80
+// on the Dirichlet set).
+__device__ __forceinline__ bool lp_learned(uint8_t info) { return info == 1; }
+
+// gfeat[e][0..5] = element means of the six factors / gd, gfeat[e][6] = gd,
+// igd[e] = 1 / gd; G in the problem's factor pairs.
 __global__ void __launch_bounds__(256)
-lp_geom_kernel(int N3, const double *__restrict__ G, float *__restrict__ gfeat)
+lp_geom_kernel(int N3, const double *__restrict__ G, float *__restrict__ gfeat,
+               double *__restrict__ igd)
 {
     __shared__ double s[4];
     const int64_t e = blockIdx.x;
@@ -65,67 +101,84 @@ lp_geom_kernel(int N3, const double *__restrict__ G, float *__restrict__ gfeat)
         const int f = threadIdx.x;
         gfeat[e * 8 + f] = f < 6 ? (float)(m[f] / gd) : (f == 6 ? (float)gd : 0.f);
     }
+    if (threadIdx.x == 0) igd[e] = 1.0 / gd;
 }
 
-// One block per padded row: X[e] = [bf16(r_e/||r_e||), gfeat[e][0..5], 0...],
-// scale[e] = ||r_e|| / gd_e; rows e >= E are zero.
-__global__ void __launch_bounds__(256)
-lp_feat_kernel(int N3, int in_pad, int64_t E, const double *__restrict__ r,
-               const float *__restrict__ gfeat, uint16_t *__restrict__ X,
-               float *__restrict__ scale, const double *__restrict__ flag)
+// F[e] = bf16 features (six, zeros to 64); rows e >= E zero.
+__global__ void lp_feat_rows_kernel(int64_t E, int64_t Epad, const float *__restrict__ gfeat,
+                                    uint16_t *__restrict__ F)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Epad * kFeat) return;
+    const int64_t e = t / kFeat;
+    const int c = (int)(t - e * kFeat);
+    F[t] = (e < E && c < 6) ? lp_f2bf(gfeat[e * 8 + c]) : (uint16_t)0;
+}
+
+__global__ void lp_softplus_kernel(int64_t n, float *__restrict__ a)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float v = a[q];
+        a[q] = log1pf(expf(-fabsf(v))) + fmaxf(v, 0.f);
+    }
+}
+
+// X[e][q] = bf16(r at interior node q) on learned nodes, 0 elsewhere and in
+// the padding (q >= nI, e >= E).
+__global__ void lp_gather_kernel(int N, int nI, int nIp, int64_t E, int64_t Epad,
+                                 const double *__restrict__ r, const uint8_t *__restrict__ info,
+                                 uint16_t *__restrict__ X, const double *__restrict__ flag)
 {
     if (flag && *flag != 0.0) return;
-    __shared__ double s[4];
-    const int64_t e = blockIdx.x;
-    uint16_t *xr = X + (size_t)e * in_pad;
-    if (e >= E) {
-        for (int q = threadIdx.x; q < in_pad; q += blockDim.x) xr[q] = 0;
-        if (threadIdx.x == 0) scale[e] = 0.f;
-        return;
+    const int64_t N3 = (int64_t)N * N * N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < Epad * nIp;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = t / nIp;
+        const int q = (int)(t - e * nIp);
+        uint16_t v = 0;
+        if (e < E && q < nI) {
+            const int64_t l = e * N3 + lp_inode(q, N);
+            if (lp_learned(info[l])) v = lp_f2bf((float)r[l]);
+        }
+        X[t] = v;
     }
-    const double *re = r + (size_t)e * N3;
-    double a = 0.0;
-    for (int q = threadIdx.x; q < N3; q += blockDim.x) a += re[q] * re[q];
-    const double nrm = sqrt(lp_block_sum(a, s));
-    const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-    for (int q = threadIdx.x; q < in_pad; q += blockDim.x) {
-        float v = 0.f;
-        if (q < N3) v = (float)(re[q] * inv);
-        else if (q < N3 + 6) v = gfeat[e * 8 + (q - N3)];
-        xr[q] = lp_f2bf(v);
-    }
-    if (threadIdx.x == 0) scale[e] = (float)(nrm / gfeat[e * 8 + 6]);
 }
 
-// zl[l] = c_l * scale[e] * Y[e][node]
-__global__ void lp_combine_kernel(int N3, int out_pad, int64_t n, const float *__restrict__ Y,
-                                  const float *__restrict__ scale,
-                                  const uint8_t *__restrict__ info, double *__restrict__ zl,
-                                  const double *__restrict__ flag)
+// z at local node l: the learned value on learned interior nodes, Jacobi
+// elsewhere.
+__device__ __forceinline__ double lp_z(int N, int64_t N3, int64_t l, double rl, double dl,
+                                       uint8_t inf, const float *__restrict__ Zi, int nIp,
+                                       const double *__restrict__ igd)
 {
-    if (flag && *flag != 0.0) return;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = l / N3;
-        const int q = (int)(l - e * N3);
-        zl[l] = sk::cw(info[l]) * (double)scale[e] * (double)Y[(size_t)e * out_pad + q];
+    const int64_t e = l / N3;
+    const int p = (int)(l - e * N3);
+    const int i = p % N, j = (p / N) % N, k = p / (N * N);
+    if (i > 0 && i < N - 1 && j > 0 && j < N - 1 && k > 0 && k < N - 1 && lp_learned(inf)) {
+        const int m = N - 2;
+        const int q = (i - 1) + m * ((j - 1) + m * (k - 1));
+        return (double)Zi[e * nIp + q] * igd[e];
     }
+    return dl * rl;
 }
 
-// z_new = dinv r + zl; partials of <r, z_new>_c and <z_new, w>_c (w = A p
-// of the step just taken; not read on the first application); z = z_new.
+// z_new from r and the learned rows; partials of <r, z_new>_c and
+// <z_new, w>_c (w = A p of the step just taken; not read on the first
+// application); z = z_new.
 __global__ void __launch_bounds__(sk::kRedThreads)
-lp_dots_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
-               const double *__restrict__ zl, const uint8_t *__restrict__ info,
-               const double *__restrict__ w, int first, double *__restrict__ z,
-               double *__restrict__ part, const double *__restrict__ scal)
+lp_dots_kernel(int N, int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
+               const uint8_t *__restrict__ info, const float *__restrict__ Zi, int nIp,
+               const double *__restrict__ igd, const double *__restrict__ w, int first,
+               double *__restrict__ z, double *__restrict__ part, const double *__restrict__ scal)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
+    const int64_t N3 = (int64_t)N * N * N;
     double a = 0, b = 0;
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
          l += (int64_t)gridDim.x * blockDim.x) {
-        const double c = sk::cw(info[l]), rl = r[l];
-        const double zn = dinv[l] * rl + zl[l];
+        const uint8_t inf = info[l];
+        const double c = sk::cw(inf), rl = r[l];
+        const double zn = lp_z(N, N3, l, rl, dinv[l], inf, Zi, nIp, igd);
         a += c * rl * zn;
         if (!first) b += c * zn * w[l];
         z[l] = zn;
@@ -202,52 +255,81 @@ lp_rr_kernel(int nb, const double *__restrict__ part, double *__restrict__ scal)
     }
 }
 
-// z = dinv r + zl (plain application, no dots)
-__global__ void lp_out_kernel(int64_t n, const double *__restrict__ r,
-                              const double *__restrict__ dinv, const double *__restrict__ zl,
-                              double *__restrict__ z)
+// z = M r (plain application, no dots)
+__global__ void lp_out_kernel(int N, int64_t n, const double *__restrict__ r,
+                              const double *__restrict__ dinv, const uint8_t *__restrict__ info,
+                              const float *__restrict__ Zi, int nIp,
+                              const double *__restrict__ igd, double *__restrict__ z)
 {
+    const int64_t N3 = (int64_t)N * N * N;
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
          l += (int64_t)gridDim.x * blockDim.x)
-        z[l] = dinv[l] * r[l] + zl[l];
+        z[l] = lp_z(N, N3, l, r[l], dinv[l], info[l], Zi, nIp, igd);
 }
 
-// Training rows for selected elements: X as in lp_feat_kernel, T[j] =
-// (e_j - dinv_j r_j) / s_e for the element's nodes (e = xs - x), 0 beyond.
+// vm = v - v0 on learned interior nodes (v0 may be null), 0 elsewhere
+__global__ void lp_mask_kernel(int N, int64_t n, const double *__restrict__ v,
+                               const double *__restrict__ v0, const uint8_t *__restrict__ info,
+                               double *__restrict__ vm)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(l % N3);
+        const int i = p % N, j = (p / N) % N, k = p / (N * N);
+        const bool in = i > 0 && i < N - 1 && j > 0 && j < N - 1 && k > 0 && k < N - 1;
+        vm[l] = (in && lp_learned(info[l])) ? (v0 ? v[l] - v0[l] : v[l]) : 0.0;
+    }
+}
+
+// Training rows for the selected elements (one block per row), from the
+// masked vector vm = v_S and y = A vm: with s = |v_S|, X = bf16(y_S / (s gd)),
+// T = v_S / s, F = bf16 features; an element index outside [0, E) or
+// v_S = 0 gives an all-zero row.
 __global__ void __launch_bounds__(256)
-lp_sample_kernel(int N3, int in_pad, int out_pad, int64_t E, const int32_t *__restrict__ elems,
-                 const double *__restrict__ r, const double *__restrict__ xs,
-                 const double *__restrict__ x, const double *__restrict__ dinv,
-                 const float *__restrict__ gfeat, uint16_t *__restrict__ X, float *__restrict__ T)
+lp_sample_kernel(int N, int nI, int nIp, int64_t E, const int32_t *__restrict__ elems,
+                 const double *__restrict__ v, const double *__restrict__ y,
+                 const uint8_t *__restrict__ info, const float *__restrict__ gfeat,
+                 const double *__restrict__ igd, uint16_t *__restrict__ X,
+                 float *__restrict__ T, uint16_t *__restrict__ F)
 {
     __shared__ double s[4];
     const int row = blockIdx.x;
     const int64_t e = elems[row];
-    uint16_t *xr = X + (size_t)row * in_pad;
-    float *tr = T + (size_t)row * out_pad;
-    if (e < 0 || e >= E) {  /* out-of-range index: an all-zero row */
-        for (int q = threadIdx.x; q < in_pad; q += blockDim.x) xr[q] = 0;
-        for (int q = threadIdx.x; q < out_pad; q += blockDim.x) tr[q] = 0.f;
+    uint16_t *xr = X + (size_t)row * nIp;
+    float *tr = T + (size_t)row * nIp;
+    uint16_t *fr = F + (size_t)row * kFeat;
+    const int64_t N3 = (int64_t)N * N * N;
+    const bool valid = e >= 0 && e < E;
+    double ss = 0.0;
+    if (valid) {
+        for (int q = threadIdx.x; q < nI; q += blockDim.x) {
+            const int64_t l = e * N3 + lp_inode(q, N);
+            if (lp_learned(info[l])) ss += v[l] * v[l];
+        }
+    }
+    const double nrm = sqrt(lp_block_sum(ss, s));
+    if (!valid || !(nrm > 0.0)) {
+        for (int q = threadIdx.x; q < nIp; q += blockDim.x) { xr[q] = 0; tr[q] = 0.f; }
+        for (int c = threadIdx.x; c < kFeat; c += blockDim.x) fr[c] = 0;
         return;
     }
-    const size_t base = (size_t)e * N3;
-    double a = 0.0;
-    for (int q = threadIdx.x; q < N3; q += blockDim.x) a += r[base + q] * r[base + q];
-    const double nrm = sqrt(lp_block_sum(a, s));
-    const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-    const double sc = nrm / gfeat[e * 8 + 6];
-    const double isc = sc > 0 ? 1.0 / sc : 0.0;
-    for (int q = threadIdx.x; q < in_pad; q += blockDim.x) {
-        float v = 0.f;
-        if (q < N3) v = (float)(r[base + q] * inv);
-        else if (q < N3 + 6) v = gfeat[e * 8 + (q - N3)];
-        xr[q] = lp_f2bf(v);
+    const double inv = 1.0 / nrm, ig = igd[e];
+    for (int q = threadIdx.x; q < nIp; q += blockDim.x) {
+        uint16_t xv = 0;
+        float tv = 0.f;
+        if (q < nI) {
+            const int64_t l = e * N3 + lp_inode(q, N);
+            if (lp_learned(info[l])) {
+                xv = lp_f2bf((float)(y[l] * inv * ig));
+                tv = (float)(v[l] * inv);
+            }
+        }
+        xr[q] = xv;
+        tr[q] = tv;
     }
-    for (int q = threadIdx.x; q < out_pad; q += blockDim.x) {
-        double t = 0.0;
-        if (q < N3) t = ((xs[base + q] - x[base + q]) - dinv[base + q] * r[base + q]) * isc;
-        tr[q] = (float)t;
-    }
+    for (int c = threadIdx.x; c < kFeat; c += blockDim.x)
+        fr[c] = c < 6 ? lp_f2bf(gfeat[e * 8 + c]) : (uint16_t)0;
 }
 
 unsigned lp_grid(int64_t n)
@@ -257,6 +339,20 @@ unsigned lp_grid(int64_t n)
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+__global__ void lp_scale_kernel(int64_t n, double a, double *__restrict__ x)
+{
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (int64_t)gridDim.x * blockDim.x)
+        x[l] = a == 0.0 ? 0.0 : a * x[l];
+}
+
+__global__ void lp_add_kernel(int64_t n, const double *__restrict__ d, double *__restrict__ x)
+{
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (int64_t)gridDim.x * blockDim.x)
+        x[l] += d[l];
+}
+
 }  // namespace
 }  // namespace nbx
 
@@ -264,12 +360,17 @@ using namespace nbx;
 
 struct nbx_lp {
     nbx_problem *P = nullptr;
-    nbx_mlp *mlp = nullptr;
-    int N3 = 0, in_pad = 0, out_pad = 0, max_batch = 0;
+    nbx_lpi *M = nullptr;
+    int N = 0, nI = 0, nIp = 0;
     int64_t E = 0, Epad = 0;
-    float *gfeat = nullptr, *Y = nullptr, *scale = nullptr;
-    uint16_t *X = nullptr;
-    double *zl = nullptr, *part4 = nullptr;
+    float *gfeat = nullptr;     // [E][8]
+    double *igd = nullptr;      // [E] 1 / gd
+    uint16_t *F = nullptr;      // [Epad][64] BF16 features
+    float *gam = nullptr;       // [Epad][nIp] gains
+    uint16_t *X = nullptr, *Qb = nullptr;   // [Epad][nIp]
+    float *Zi = nullptr;        // [Epad][nIp]
+    double *part4 = nullptr;
+    double *vm = nullptr, *ym = nullptr;    // sampling work vectors (first use)
     hipGraphExec_t gexec = nullptr;
     const double *g_x = nullptr;
     int g_iters = 0, g_tile = 0;
@@ -278,34 +379,55 @@ struct nbx_lp {
 namespace nbx {
 namespace {
 
-// zl = mask(dssum(c * s * f(features(r)))) ; flag may be null
-int enqueue_correction(nbx_lp *L, const double *r, const double *flag, hipStream_t s)
+// gamma for every element from the current model
+int compute_gains(nbx_lp *L, hipStream_t s)
 {
-    nbx_problem *P = L->P;
-    hipLaunchKernelGGL(lp_feat_kernel, dim3((unsigned)L->Epad), dim3(256), 0, s, L->N3,
-                       L->in_pad, P->E, r, L->gfeat, L->X, L->scale, flag);
-    NBX_LAUNCH_CHECK();
-    for (int64_t r0 = 0; r0 < L->Epad; r0 += L->max_batch) {
-        const int rows = (int)std::min<int64_t>(L->max_batch, L->Epad - r0);
-        int st = mlp_forward_rows(L->mlp, L->X + (size_t)r0 * L->in_pad, rows,
-                                  L->Y + (size_t)r0 * L->out_pad, s);
+    nbx_mlp *mlp = lpi_mlp(L->M);
+    const int mb = lpi_max_batch(L->M);
+    for (int64_t r0 = 0; r0 < L->Epad; r0 += mb) {
+        const int rows = (int)std::min<int64_t>(mb, L->Epad - r0);
+        int st = mlp_forward_rows(mlp, L->F + (size_t)r0 * kFeat, rows,
+                                  L->gam + (size_t)r0 * L->nIp, s);
         if (st != NBX_OK) return st;
     }
-    hipLaunchKernelGGL(lp_combine_kernel, dim3(lp_grid(P->n)), dim3(256), 0, s, L->N3,
-                       L->out_pad, P->n, L->Y, L->scale, P->gs->plan.info, L->zl, flag);
+    const int64_t n = L->Epad * L->nIp;
+    hipLaunchKernelGGL(lp_softplus_kernel, dim3(lp_grid(n)), dim3(256), 0, s, n, L->gam);
     NBX_LAUNCH_CHECK();
-    return dssum_launch<double>(P->gs->plan, L->zl, 1, s, flag);
+    return NBX_OK;
+}
+
+// Zi = ((X L^T) * gamma) L for X = gather(r); flag may be null
+int enqueue_rows(nbx_lp *L, const double *r, const double *flag, hipStream_t s)
+{
+    nbx_problem *P = L->P;
+    const int n = L->nIp;
+    hipLaunchKernelGGL(lp_gather_kernel, dim3(lp_grid(L->Epad * n)), dim3(256), 0, s, L->N,
+                       L->nI, n, P->E, L->Epad, r, P->gs->plan.info, L->X, flag);
+    NBX_LAUNCH_CHECK();
+    const uint16_t *Lb = lpi_Lb(L->M);
+    for (int64_t r0 = 0; r0 < L->Epad; r0 += kGemmRows) {
+        const int rows = (int)std::min<int64_t>(kGemmRows, L->Epad - r0);
+        const size_t o = (size_t)r0 * n;
+        int st = gemm_bf16(0, 1, kEpiMulBf16, rows, n, n, L->X + o, n, Lb, n, nullptr, 0,
+                           L->Qb + o, n, nullptr, nullptr, n, s, L->gam + o);
+        if (st != NBX_OK) return st;
+        st = gemm_bf16(0, 0, kEpiF32, rows, n, n, L->Qb + o, n, Lb, n, L->Zi + o, n, nullptr, 0,
+                       nullptr, nullptr, 0, s, nullptr);
+        if (st != NBX_OK) return st;
+    }
+    return NBX_OK;
 }
 
 // z <- M(r) inside the flexible iteration, with the dots and beta.
 int enqueue_precond(nbx_lp *L, double *scal, int first, hipStream_t s)
 {
     nbx_problem *P = L->P;
-    int st = enqueue_correction(L, P->r, scal + NBX_S_FLAG, s);
+    int st = enqueue_rows(L, P->r, scal + NBX_S_FLAG, s);
     if (st != NBX_OK) return st;
     const int nb = sk::red_blocks(P->n);
-    hipLaunchKernelGGL(lp_dots_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n, P->r,
-                       P->dinv, L->zl, P->gs->plan.info, P->w, first, P->z, L->part4, scal);
+    hipLaunchKernelGGL(lp_dots_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, L->N, P->n, P->r,
+                       P->dinv, P->gs->plan.info, L->Zi, L->nIp, L->igd, P->w, first, P->z,
+                       L->part4, scal);
     hipLaunchKernelGGL(lp_beta_kernel, dim3(1), dim3(1024), 0, s, nb, L->part4, scal, first);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
@@ -334,62 +456,64 @@ int enqueue_flex_iters(nbx_lp *L, double *x, int n_iter, hipStream_t s)
     return NBX_OK;
 }
 
-__global__ void lp_scale_kernel(int64_t n, double a, double *__restrict__ x)
-{
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x)
-        x[l] = a == 0.0 ? 0.0 : a * x[l];
-}
-
-__global__ void lp_add_kernel(int64_t n, const double *__restrict__ d, double *__restrict__ x)
-{
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x)
-        x[l] += d[l];
-}
-
 }  // namespace
 }  // namespace nbx
-
-extern "C" int nbx_lp_create(nbx_problem *P, nbx_mlp *mlp, nbx_lp **out, void *stream)
-{
-    if (!out) return NBX_EINVAL;
-    *out = nullptr;
-    if (!P || !mlp) return NBX_EINVAL;
-    int n_in, n_out, in_pad, out_pad, max_batch;
-    mlp_dims(mlp, &n_in, &n_out, &in_pad, &out_pad, &max_batch);
-    const int N3 = P->N * P->N * P->N;
-    if (n_in != N3 + 6 || n_out != N3) return NBX_EINVAL;
-    nbx_lp *L = new (std::nothrow) nbx_lp;
-    if (!L) return NBX_ENOMEM;
-    L->P = P; L->mlp = mlp; L->N3 = N3; L->in_pad = in_pad; L->out_pad = out_pad;
-    L->max_batch = max_batch; L->E = P->E; L->Epad = (P->E + 63) / 64 * 64;
-    const size_t Ep = (size_t)L->Epad;
-    if (hipMalloc(&L->gfeat, (size_t)P->E * 8 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&L->X, Ep * in_pad * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&L->Y, Ep * out_pad * sizeof(float)) != hipSuccess ||
-        hipMalloc(&L->scale, Ep * sizeof(float)) != hipSuccess ||
-        hipMalloc(&L->zl, (size_t)P->n * sizeof(double)) != hipSuccess ||
-        hipMalloc(&L->part4, 2 * sk::kMaxRedBlocks * sizeof(double)) != hipSuccess) {
-        nbx_lp_destroy(L);
-        return NBX_ENOMEM;
-    }
-    hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(lp_geom_kernel, dim3((unsigned)P->E), dim3(256), 0, s, N3, P->G, L->gfeat);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) { nbx_lp_destroy(L); return hip_fail(e, "lp_create"); }
-    *out = L;
-    return NBX_OK;
-}
 
 extern "C" int nbx_lp_destroy(nbx_lp *L)
 {
     if (!L) return NBX_OK;
     if (L->gexec) hipGraphExecDestroy(L->gexec);
-    hipFree(L->gfeat); hipFree(L->X); hipFree(L->Y); hipFree(L->scale); hipFree(L->zl);
-    hipFree(L->part4);
+    hipFree(L->gfeat); hipFree(L->igd); hipFree(L->F); hipFree(L->gam); hipFree(L->X);
+    hipFree(L->Qb); hipFree(L->Zi); hipFree(L->part4); hipFree(L->vm); hipFree(L->ym);
     delete L;
+    return NBX_OK;
+}
+
+extern "C" int nbx_lp_refresh(nbx_lp *L, void *stream)
+{
+    if (!L) return NBX_EINVAL;
+    hipStream_t s = as_stream(stream);
+    int st = compute_gains(L, s);
+    if (st != NBX_OK) return st;
+    NBX_HIP(hipStreamSynchronize(s));
+    return NBX_OK;
+}
+
+extern "C" int nbx_lp_create(nbx_problem *P, nbx_lpi *M, nbx_lp **out, void *stream)
+{
+    if (!out) return NBX_EINVAL;
+    *out = nullptr;
+    if (!P || !M) return NBX_EINVAL;
+    int N, nI, nIp;
+    lpi_dims(M, &N, &nI, &nIp);
+    if (N != P->N) return NBX_EINVAL;
+    nbx_lp *L = new (std::nothrow) nbx_lp;
+    if (!L) return NBX_ENOMEM;
+    L->P = P; L->M = M; L->N = N; L->nI = nI; L->nIp = nIp;
+    L->E = P->E; L->Epad = (P->E + 63) / 64 * 64;
+    const size_t Ep = (size_t)L->Epad, rows = Ep * nIp;
+    if (hipMalloc(&L->gfeat, (size_t)P->E * 8 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&L->igd, (size_t)P->E * sizeof(double)) != hipSuccess ||
+        hipMalloc(&L->F, Ep * kFeat * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&L->gam, rows * sizeof(float)) != hipSuccess ||
+        hipMalloc(&L->X, rows * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&L->Qb, rows * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&L->Zi, rows * sizeof(float)) != hipSuccess ||
+        hipMalloc(&L->part4, 2 * sk::kMaxRedBlocks * sizeof(double)) != hipSuccess) {
+        nbx_lp_destroy(L);
+        return NBX_ENOMEM;
+    }
+    hipStream_t s = as_stream(stream);
+    const int N3 = N * N * N;
+    hipLaunchKernelGGL(lp_geom_kernel, dim3((unsigned)P->E), dim3(256), 0, s, N3, P->G, L->gfeat,
+                       L->igd);
+    hipLaunchKernelGGL(lp_feat_rows_kernel, dim3((unsigned)((Ep * kFeat + 255) / 256)), dim3(256),
+                       0, s, P->E, L->Epad, L->gfeat, L->F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { nbx_lp_destroy(L); return hip_fail(e, "lp_create"); }
+    const int st = nbx_lp_refresh(L, stream);
+    if (st != NBX_OK) { nbx_lp_destroy(L); return st; }
+    *out = L;
     return NBX_OK;
 }
 
@@ -405,22 +529,34 @@ extern "C" int nbx_lp_apply(nbx_lp *L, const double *r, double *z, void *stream)
 {
     if (!L || !r || !z || r == z) return NBX_EINVAL;
     hipStream_t s = as_stream(stream);
-    int st = enqueue_correction(L, r, nullptr, s);
+    int st = enqueue_rows(L, r, nullptr, s);
     if (st != NBX_OK) return st;
-    hipLaunchKernelGGL(lp_out_kernel, dim3(lp_grid(L->P->n)), dim3(256), 0, s, L->P->n, r,
-                       L->P->dinv, L->zl, z);
+    nbx_problem *P = L->P;
+    hipLaunchKernelGGL(lp_out_kernel, dim3(lp_grid(P->n)), dim3(256), 0, s, L->N, P->n, r,
+                       P->dinv, P->gs->plan.info, L->Zi, L->nIp, L->igd, z);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
 }
 
-extern "C" int nbx_lp_samples(nbx_lp *L, const double *r, const double *xstar, const double *x,
-                              const int32_t *elems, int nsel, void *X, float *T, void *stream)
+extern "C" int nbx_lp_samples(nbx_lp *L, const double *v, const double *v0,
+                              const int32_t *elems, int nsel, void *X, float *T, void *F,
+                              void *stream)
 {
-    if (!L || !r || !xstar || !x || !elems || !X || !T || nsel < 0) return NBX_EINVAL;
+    if (!L || !v || !elems || !X || !T || !F || nsel < 0) return NBX_EINVAL;
     if (nsel == 0) return NBX_OK;
-    hipLaunchKernelGGL(lp_sample_kernel, dim3(nsel), dim3(256), 0, as_stream(stream), L->N3,
-                       L->in_pad, L->out_pad, L->P->E, elems, r, xstar, x, L->P->dinv, L->gfeat,
-                       (uint16_t *)X, T);
+    nbx_problem *P = L->P;
+    const size_t vb = sizeof(double) * (size_t)P->n;
+    if (!L->vm && hipMalloc(&L->vm, vb) != hipSuccess) return NBX_ENOMEM;
+    if (!L->ym && hipMalloc(&L->ym, vb) != hipSuccess) return NBX_ENOMEM;
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(lp_mask_kernel, dim3(lp_grid(P->n)), dim3(256), 0, s, L->N, P->n, v, v0,
+                       P->gs->plan.info, L->vm);
+    NBX_LAUNCH_CHECK();
+    int st = ax_launch_f64(L->vm, P->G, P->D, P->N, P->E, L->ym, s);
+    if (st != NBX_OK) return st;
+    hipLaunchKernelGGL(lp_sample_kernel, dim3(nsel), dim3(256), 0, s, L->N, L->nI, L->nIp, P->E,
+                       elems, L->vm, L->ym, P->gs->plan.info, L->gfeat, L->igd, (uint16_t *)X, T,
+                       (uint16_t *)F);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
 }
@@ -497,9 +633,11 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
     st = residual_f64(P, b, x, P->r, rb, s);
     if (st != NBX_OK) return st;
     double relres = rb[1] > 0 ? std::sqrt(rb[0] / rb[1]) : 0.0;
-    if (res->flag != 1 && relres > o.rtol) {
-        // fallback: Jacobi-PCG on the residual equation from the current x,
-        // or on A x = b from x = 0 when the flexible iteration diverged
+    const int left = o.max_iter - res->iters;
+    if (res->flag == 2 && left > 0) {
+        // breakdown: Jacobi-PCG on the residual equation from the current x
+        // (from x = 0 if the flexible iterate diverged), within the
+        // iterations the caller's budget has left
         res->fell_back = 1;
         const bool restart = !(relres < 1.0);
         double *rhs = nullptr, *d = nullptr;
@@ -516,7 +654,7 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
         nbx_pcg_opts o64 = o;
         o64.prec = NBX_F64;
         o64.rtol = (relres > 0 && !restart) ? o.rtol / relres : o.rtol;
-        o64.max_iter = std::max(2 * o.max_iter, 1000);
+        o64.max_iter = left;
         nbx_pcg_result r64{};
         st = pcg_f64(P, rhs, d, o64, &r64);
         if (st == NBX_OK) {

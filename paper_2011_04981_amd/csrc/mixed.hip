@@ -116,7 +116,7 @@ int prepare_inner(nbx_problem *P, int fmt, hipStream_t s)
                 return NBX_ENOMEM;
             }
         }
-        int st = nbx_g16_pack(fmt, P->G, P->N, P->E, P->G16, P->gscale, s);
+        int st = g16_pack_launch(fmt, 0, P->G, P->N, P->E, P->G16, P->gscale, s);
         if (st != NBX_OK) return st;
         P->g16_fmt = fmt;
     }
@@ -299,6 +299,15 @@ int reliable_start(nbx_problem *P, const double *b, double *x, const nbx_pcg_opt
     return NBX_OK;
 }
 
+namespace {
+
+// Ends a problem's FP32 iterations on the device: every later launch of its
+// stages (a batch keeps replaying all problems) returns at once, so ITER
+// and the state stay as the host's decision left them.
+__global__ void stop_kernel(double *scal) { scal[NBX_S_FLAG] = sk::kFlagLimit; }
+
+}  // namespace
+
 int reliable_step(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
                   const double *h, ReliableState &rs, hipStream_t s)
 {
@@ -334,8 +343,11 @@ int reliable_step(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts
     else rs.stalls = 0;
     rs.last_true = g[kSlotTrue];
     if (rs.stalls >= 2 || rs.updates >= o.max_outer) {
+        // the device flag reads 0 (continue) here: make it terminal
         rs.fell_back = rs.stalls >= 2;
         rs.done = 1;
+        hipLaunchKernelGGL(stop_kernel, dim3(1), dim3(1), 0, s, P->scal32);
+        NBX_LAUNCH_CHECK();
     }
     return NBX_OK;
 }

@@ -28,9 +28,11 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
-enum Epi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_BIAS_F32 = 2, EPI_RELU_GRAD_BF16 = 3 };
+enum Epi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_BIAS_F32 = 2, EPI_RELU_GRAD_BF16 = 3,
+           EPI_ACC_F32 = 4, EPI_MUL_BF16 = 5 };
 
 constexpr int TM = 64, TN = 64, TK = 32, LDS_PAD = 8;
+constexpr int kLossBlocks = 1024;   // partial sums of the squared-error loss
 
 // C[M x N] = op(A)[M x K] op(B)[K x N], BF16 operands, FP32 accumulation.
 //   A element (m,k): TA ? A[k*lda + m] : A[m*lda + k]
@@ -40,12 +42,16 @@ constexpr int TM = 64, TN = 64, TK = 32, LDS_PAD = 8;
 // 32x32 quarter as 2x2 16x16x32 MFMA tiles.  Operand tiles are staged in
 // LDS K-contiguous ([m][k] and [n][k]) so every lane's 8-element MFMA
 // operand is one 16-byte LDS read.
+// Epilogues: EPI_F32 C = v; EPI_ACC_F32 C += v; EPI_BIAS_F32 C = v + bias[n];
+// EPI_BIAS_RELU_BF16 Cb = bf16(relu(v + bias[n])); EPI_RELU_GRAD_BF16
+// Cb = bf16(v) where the BF16 activation act[m][n] is positive, else 0;
+// EPI_MUL_BF16 Cb = bf16(v * mul[m][n]) (mul FP32, leading dimension ldact).
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256)
 gemm_bf16_kernel(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
                  const uint16_t *__restrict__ B, int ldb, float *__restrict__ C, int ldc,
                  uint16_t *__restrict__ Cb, int ldcb, const float *__restrict__ bias,
-                 const uint16_t *__restrict__ act, int ldact)
+                 const uint16_t *__restrict__ act, int ldact, const float *__restrict__ mul)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][TK + LDS_PAD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][TK + LDS_PAD];
@@ -104,6 +110,10 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
                 float v = acc[a][b][i];
                 if (EPI == EPI_F32) {
                     C[(size_t)m * ldc + n] = v;
+                } else if (EPI == EPI_ACC_F32) {
+                    C[(size_t)m * ldc + n] += v;
+                } else if (EPI == EPI_MUL_BF16) {
+                    Cb[(size_t)m * ldcb + n] = f2bf(v * mul[(size_t)m * ldact + n]);
                 } else if (EPI == EPI_BIAS_F32) {
                     C[(size_t)m * ldc + n] = v + bias[n];
                 } else if (EPI == EPI_BIAS_RELU_BF16) {
@@ -120,31 +130,34 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
 template <bool TA, bool TB, int EPI>
 void launch_gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
                  float *C, int ldc, uint16_t *Cb, int ldcb, const float *bias,
-                 const uint16_t *act, int ldact, hipStream_t s)
+                 const uint16_t *act, int ldact, const float *mul, hipStream_t s)
 {
     hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), dim3(N / TN, M / TM), dim3(256), 0, s, M,
-                       N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact);
+                       N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, mul);
 }
 
 int gemm(int ta, int tb, int epi, int M, int N, int K, const uint16_t *A, int lda,
          const uint16_t *B, int ldb, float *C, int ldc, uint16_t *Cb, int ldcb, const float *bias,
-         const uint16_t *act, int ldact, hipStream_t s)
+         const uint16_t *act, int ldact, hipStream_t s, const float *mul = nullptr)
 {
     if (M <= 0 || N <= 0 || K <= 0 || M % TM || N % TN || K % TK) return NBX_EINVAL;
     if (lda % 8 || ldb % 8) return NBX_EINVAL;
     if (!A || !B) return NBX_EINVAL;
-    if ((epi == EPI_F32 || epi == EPI_BIAS_F32) && !C) return NBX_EINVAL;
-    if ((epi == EPI_BIAS_RELU_BF16 || epi == EPI_RELU_GRAD_BF16) && !Cb) return NBX_EINVAL;
+    if ((epi == EPI_F32 || epi == EPI_BIAS_F32 || epi == EPI_ACC_F32) && !C) return NBX_EINVAL;
+    if ((epi == EPI_BIAS_RELU_BF16 || epi == EPI_RELU_GRAD_BF16 || epi == EPI_MUL_BF16) && !Cb)
+        return NBX_EINVAL;
     if ((epi == EPI_BIAS_F32 || epi == EPI_BIAS_RELU_BF16) && !bias) return NBX_EINVAL;
     if (epi == EPI_RELU_GRAD_BF16 && !act) return NBX_EINVAL;
+    if (epi == EPI_MUL_BF16 && !mul) return NBX_EINVAL;
 #define NBX_G(TA_, TB_, E_)                                                                 \
     if (ta == TA_ && tb == TB_ && epi == E_) {                                              \
-        launch_gemm<TA_, TB_, E_>(M, N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, s); \
+        launch_gemm<TA_, TB_, E_>(M, N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, \
+                                  mul, s);                                                  \
         NBX_LAUNCH_CHECK();                                                                 \
         return NBX_OK;                                                                      \
     }
     NBX_G(0, 0, 0) NBX_G(0, 1, 0) NBX_G(1, 0, 0) NBX_G(1, 1, 0)
-    NBX_G(0, 1, 1) NBX_G(0, 1, 2) NBX_G(0, 0, 3)
+    NBX_G(0, 1, 1) NBX_G(0, 1, 2) NBX_G(0, 0, 3) NBX_G(1, 0, 4) NBX_G(0, 1, 5)
 #undef NBX_G
     return NBX_EUNSUPPORTED;
 }
@@ -265,9 +278,40 @@ unsigned grid_for(int64_t n)
 
 int gemm_bf16(int ta, int tb, int epi, int M, int N, int K, const uint16_t *A, int lda,
               const uint16_t *B, int ldb, float *C, int ldc, uint16_t *Cb, int ldcb,
-              const float *bias, const uint16_t *act, int ldact, hipStream_t s)
+              const float *bias, const uint16_t *act, int ldact, hipStream_t s,
+              const float *mul)
 {
-    return gemm(ta, tb, epi, M, N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, s);
+    return gemm(ta, tb, epi, M, N, K, A, lda, B, ldb, C, ldc, Cb, ldcb, bias, act, ldact, s,
+                mul);
+}
+
+int mse_grad(int B, int n_pad, int n_out, const float *Y, const float *T, float *dY,
+             uint16_t *dYb, double *part, double *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(kLossBlocks), dim3(256), 0, s, B, n_pad, n_out, Y,
+                       T, dY, dYb, part);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, kLossBlocks, part,
+                       1.0 / ((double)B * n_out), loss);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+int adam_update(int64_t n, float *w, uint16_t *wb, float *m, float *v, const float *g, float lr,
+                int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, w, wb, m, v, g, lr,
+                       b1, b2, eps, c1, c2);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+int to_bf16(int64_t n, const float *a, uint16_t *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, a, b);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
 }
 
 int mlp_forward_rows(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s);
@@ -302,8 +346,6 @@ struct nbx_mlp {
 namespace nbx {
 namespace {
 
-constexpr int kLossBlocks = 1024;
-
 // out[N] = column sums of X [M x N] (M, N multiples of 64; part holds
 // M/64 x N floats).
 template <bool BF>
@@ -334,17 +376,12 @@ int mlp_forward(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s)
                 P->n_hid, Y, P->out_pad, nullptr, 0, w + P->ob3(), nullptr, 0, s);
 }
 
-// Gradients of the mean squared error over the first n_out outputs into
-// P->g, loss into P->loss (device).
-int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream_t s)
+// Gradients of every parameter into P->g from the output gradient already in
+// P->dY (FP32) and P->dYb (BF16), for the B rows of X whose forward pass
+// left H1, H2 in the activation buffers.
+int mlp_backprop(nbx_mlp *P, const uint16_t *X, int B, hipStream_t s)
 {
-    int st = mlp_forward(P, X, B, P->Y, s);
-    if (st != NBX_OK) return st;
-    hipLaunchKernelGGL(loss_grad_kernel, dim3(kLossBlocks), dim3(256), 0, s, B, P->out_pad,
-                       P->n_out, P->Y, T, P->dY, P->dYb, P->part);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, kLossBlocks, P->part,
-                       1.0 / ((double)B * P->n_out), P->loss);
-    NBX_LAUNCH_CHECK();
+    int st;
     const uint16_t *wb = P->wb;
     float *g = P->g;
     // layer 3: dW3 = dY^T H2, db3 = colsum dY, dH2 = (dY W3) * relu'(H2)
@@ -374,6 +411,20 @@ int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream
     return NBX_OK;
 }
 
+// Gradients of the mean squared error over the first n_out outputs into
+// P->g, loss into P->loss (device).
+int mlp_backward(nbx_mlp *P, const uint16_t *X, const float *T, int B, hipStream_t s)
+{
+    int st = mlp_forward(P, X, B, P->Y, s);
+    if (st != NBX_OK) return st;
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(kLossBlocks), dim3(256), 0, s, B, P->out_pad,
+                       P->n_out, P->Y, T, P->dY, P->dYb, P->part);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, kLossBlocks, P->part,
+                       1.0 / ((double)B * P->n_out), P->loss);
+    NBX_LAUNCH_CHECK();
+    return mlp_backprop(P, X, B, s);
+}
+
 }  // namespace
 
 int mlp_forward_rows(nbx_mlp *P, const uint16_t *X, int B, float *Y, hipStream_t s)
@@ -389,6 +440,34 @@ int mlp_dims(nbx_mlp *P, int *n_in, int *n_out, int *in_pad, int *out_pad, int *
     *max_batch = P->max_batch;
     return NBX_OK;
 }
+
+// For a composite model: the output-gradient buffers (FP32 and BF16,
+// [max_batch][out_pad]) to fill before mlp_backprop_rows, which then forms
+// every parameter's gradient for the B rows of X last run forward with
+// mlp_forward_rows; mlp_adam applies one Adam step to all parameters.
+int mlp_grad_buffers(nbx_mlp *P, float **dY, uint16_t **dYb)
+{
+    if (!P) return NBX_EINVAL;
+    *dY = P->dY; *dYb = P->dYb;
+    return NBX_OK;
+}
+
+int mlp_backprop_rows(nbx_mlp *P, const uint16_t *X, int B, hipStream_t s)
+{
+    if (!P || B < 64 || B % 64 || B > P->max_batch) return NBX_EINVAL;
+    return mlp_backprop(P, X, B, s);
+}
+
+int mlp_adam(nbx_mlp *P, float lr, hipStream_t s)
+{
+    P->step += 1;
+    return adam_update(P->n_par, P->w, P->wb, P->m, P->v, P->g, lr, P->step, s);
+}
+
+int64_t mlp_nparams(nbx_mlp *P) { return P ? P->n_par : 0; }
+int64_t mlp_last_bias(nbx_mlp *P, int *n) { *n = P->out_pad; return P->ob3(); }
+float *mlp_weights(nbx_mlp *P) { return P ? P->w : nullptr; }
+float *mlp_grads(nbx_mlp *P) { return P ? P->g : nullptr; }
 
 }  // namespace nbx
 
@@ -455,10 +534,11 @@ extern "C" int nbx_mlp_shape(nbx_mlp *P, int *in_pad, int *out_pad, int64_t *n_p
     return NBX_OK;
 }
 
-extern "C" int nbx_mlp_set_params(nbx_mlp *P, const float *params, void *stream)
+namespace nbx {
+
+int mlp_set_params(nbx_mlp *P, const float *params, hipStream_t s)
 {
     if (!P || !params) return NBX_EINVAL;
-    hipStream_t s = as_stream(stream);
     NBX_HIP(hipMemcpyAsync(P->w, params, (size_t)P->n_par * 4, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(P->n_par)), dim3(256), 0, s, P->n_par, P->w,
                        P->wb);
@@ -467,6 +547,13 @@ extern "C" int nbx_mlp_set_params(nbx_mlp *P, const float *params, void *stream)
     NBX_HIP(hipMemsetAsync(P->v, 0, (size_t)P->n_par * 4, s));
     P->step = 0;
     return NBX_OK;
+}
+
+}  // namespace nbx
+
+extern "C" int nbx_mlp_set_params(nbx_mlp *P, const float *params, void *stream)
+{
+    return mlp_set_params(P, params, as_stream(stream));
 }
 
 extern "C" int nbx_mlp_get_params(nbx_mlp *P, float *params, float *grads, void *stream)
@@ -503,12 +590,5 @@ extern "C" int nbx_mlp_train_step(nbx_mlp *P, const void *X, const float *T, int
     if (!(lr > 0)) return NBX_EINVAL;
     int st = nbx_mlp_grad(P, X, T, B, loss, stream);
     if (st != NBX_OK) return st;
-    hipStream_t s = as_stream(stream);
-    P->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - std::pow(b1, (float)P->step), c2 = 1.f - std::pow(b2, (float)P->step);
-    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(P->n_par)), dim3(256), 0, s, P->n_par, P->w,
-                       P->wb, P->m, P->v, P->g, lr, b1, b2, eps, c1, c2);
-    NBX_LAUNCH_CHECK();
-    return NBX_OK;
+    return mlp_adam(P, lr, as_stream(stream));
 }

@@ -25,27 +25,47 @@ namespace nbx {
 int jacobi_setup_impl(const double *G, const double *D, int N, int64_t E, const GsPlan &gs,
                       double *dinv, hipStream_t s);
 
+// What one fused FP64 iteration reads and writes: the operator (factor
+// pairs Gp, D, N, E), the exchange plan, dinv, the state vectors, w (A p of
+// the last step) and the two partial-sum buffers (part1: one double per
+// fused-stage workgroup, ax_blocks(); part3: 2 * red_blocks(n) doubles).
+struct IterArgs {
+    const double *Gp, *D, *dinv;
+    int N;
+    int64_t E, n;
+    const GsPlan *gs;
+    double *w, *part1, *part3;
+};
+
 // Enqueues n_iter fused FP64 iterations on s.
-static int enqueue_iters(nbx_problem *P, double *x, double *r, double *z, double *p,
-                         double *scal, int n_iter, hipStream_t s)
+static int enqueue_iters_on(const IterArgs &a, double *x, double *r, double *z, double *p,
+                            double *scal, int n_iter, hipStream_t s)
 {
-    const GsPlan &gs = P->gs->plan;
-    const int nb1 = ax_blocks(NBX_F64, P->N, P->E);
-    const int nb3 = sk::red_blocks(P->n);
+    const GsPlan &gs = *a.gs;
+    const int nb1 = ax_blocks(NBX_F64, a.N, a.E);
+    const int nb3 = sk::red_blocks(a.n);
     for (int it = 0; it < n_iter; ++it) {
-        int st = ax_pcg_launch_f64(P->G, P->D, P->N, P->E, z, p, P->w, P->part1, scal, s);
+        int st = ax_pcg_launch_f64(a.Gp, a.D, a.N, a.E, z, p, a.w, a.part1, scal, s);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, P->part1,
+        hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, a.part1,
                            scal);
-        st = dssum_launch<double>(gs, P->w, 1, s, scal + NBX_S_FLAG);
+        st = dssum_launch<double>(gs, a.w, 1, s, scal + NBX_S_FLAG);
         if (st != NBX_OK) return st;
         hipLaunchKernelGGL(sk::update_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
-                           P->n, p, P->w, P->dinv, gs.info, x, r, z, P->part3, scal);
-        hipLaunchKernelGGL(sk::rr_reduce_kernel, dim3(1), dim3(1024), 0, s, nb3, P->part3,
+                           a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal);
+        hipLaunchKernelGGL(sk::rr_reduce_kernel, dim3(1), dim3(1024), 0, s, nb3, a.part3,
                            scal);
         NBX_LAUNCH_CHECK();
     }
     return NBX_OK;
+}
+
+static int enqueue_iters(nbx_problem *P, double *x, double *r, double *z, double *p,
+                         double *scal, int n_iter, hipStream_t s)
+{
+    const IterArgs a{P->G, P->D, P->dinv, P->N, P->E, P->n, &P->gs->plan,
+                     P->w, P->part1, P->part3};
+    return enqueue_iters_on(a, x, r, z, p, scal, n_iter, s);
 }
 
 int residual_f64(nbx_problem *P, const double *b, const double *x, double *r, double out[2],
@@ -144,9 +164,11 @@ extern "C" int nbx_problem_create(const double *G, const double *D, int N, int64
     if (gs->plan.n_local != n) return NBX_EINVAL;
     nbx_problem *P = new (std::nothrow) nbx_problem;
     if (!P) return NBX_ENOMEM;
-    P->G = G; P->D = D; P->N = N; P->E = E; P->n = n; P->gs = gs;
+    P->D = D; P->N = N; P->E = E; P->n = n; P->gs = gs;
     auto fail = [&](int st) { nbx_problem_destroy(P); return st; };
     const size_t vb = sizeof(double) * (size_t)n;
+    if (hipMalloc(&P->Gown, 6 * vb) != hipSuccess) return fail(NBX_ENOMEM);
+    P->G = P->Gown;
     if (hipMalloc(&P->dinv, vb) != hipSuccess || hipMalloc(&P->r, vb) != hipSuccess ||
         hipMalloc(&P->z, vb) != hipSuccess || hipMalloc(&P->p, vb) != hipSuccess ||
         hipMalloc(&P->w, vb) != hipSuccess ||
@@ -163,7 +185,9 @@ extern "C" int nbx_problem_create(const double *G, const double *D, int N, int64
     e = hipEventCreateWithFlags(&P->ev, hipEventDisableTiming);
     if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
     hipStream_t s = as_stream(stream);
-    int st = jacobi_setup_impl(G, D, N, E, gs->plan, P->dinv, s);
+    int st = pair_factors_launch(G, P->Gown, N, E, s);
+    if (st != NBX_OK) return fail(st);
+    st = jacobi_setup_impl(G, D, N, E, gs->plan, P->dinv, s);
     if (st != NBX_OK) return fail(st);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize"));
@@ -177,6 +201,7 @@ extern "C" int nbx_problem_destroy(nbx_problem *P)
     if (P->ws) hipStreamSynchronize(P->ws);
     if (P->gexec) hipGraphExecDestroy(P->gexec);
     if (P->gexec32) hipGraphExecDestroy(P->gexec32);
+    hipFree(P->Gown);
     hipFree(P->dinv); hipFree(P->r); hipFree(P->z); hipFree(P->p); hipFree(P->w);
     hipFree(P->part1); hipFree(P->part3); hipFree(P->scal); hipFree(P->tmp2);
     hipFree(P->G32); hipFree(P->dinv32); hipFree(P->r32); hipFree(P->z32); hipFree(P->p32);

@@ -152,7 +152,7 @@ __global__ void geom_kernel(int N, int64_t E, GllTab tab, BrickDesc brick,
         for (int f = 0; f < 6; ++f) {
             const int a = fa[f], b = fb[f];
             const double dot = Cf[0][a] * Cf[0][b] + Cf[1][a] * Cf[1][b] + Cf[2][a] * Cf[2][b];
-            G[g_index(e, f, n, N3)] = W * dot / det;
+            G[gp_index(e, f, n, N3)] = W * dot / det;
         }
         if (bm) bm[(size_t)e * N3 + n] = W * det;
     }
@@ -175,13 +175,13 @@ __global__ void jacobi_diag_kernel(int N, int64_t E, const double *__restrict__ 
     double s = 0.0;
     for (int m = 0; m < N; ++m) {
         const double a = D[m * N + i], b = D[m * N + j], c = D[m * N + k];
-        s += a * a * G[g_index(e, 0, m + N * (j + N * k), N3)];
-        s += b * b * G[g_index(e, 3, i + N * (m + N * k), N3)];
-        s += c * c * G[g_index(e, 5, i + N * (j + N * m), N3)];
+        s += a * a * G[gp_index(e, 0, m + N * (j + N * k), N3)];
+        s += b * b * G[gp_index(e, 3, i + N * (m + N * k), N3)];
+        s += c * c * G[gp_index(e, 5, i + N * (j + N * m), N3)];
     }
     const double di = D[i * N + i], dj = D[j * N + j], dk = D[k * N + k];
-    s += 2.0 * (di * dj * G[g_index(e, 1, n, N3)] + di * dk * G[g_index(e, 2, n, N3)] +
-                dj * dk * G[g_index(e, 4, n, N3)]);
+    s += 2.0 * (di * dj * G[gp_index(e, 1, n, N3)] + di * dk * G[gp_index(e, 2, n, N3)] +
+                dj * dk * G[gp_index(e, 4, n, N3)]);
     diag[l] = s;
 }
 
@@ -211,10 +211,10 @@ __global__ void sine_source_kernel(int64_t n, const double *__restrict__ xyz,
 }
 
 // g(6, N^3, E) with the factor index fastest (the layout of the operator's
-// g argument in Section II-B) to planes of factor pairs: a block stages 256
-// nodes' six factors, contiguous in the source, in LDS and writes them
-// pair by pair, consecutive nodes of one pair plane being contiguous in the
-// target.
+// g argument in Section II-B) to one plane per factor, [E][6][N^3]: a block
+// stages 256 nodes' six factors, contiguous in the source, in LDS and
+// writes them plane by plane, consecutive nodes of a plane being
+// contiguous in the target.
 constexpr int kRepackNodes = 256;
 typedef double dpair __attribute__((ext_vector_type(2)));
 
@@ -231,14 +231,9 @@ repack_g_kernel(int64_t n, int N3, const double *__restrict__ src, double *__res
     if ((int)threadIdx.x < cnt) {
         const int64_t l = l0 + threadIdx.x;
         const int64_t e = l / N3, p = l - e * N3;
-        dpair *d = reinterpret_cast<dpair *>(dst) + e * 3 * N3 + p;
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
-            dpair v;
-            v.x = s[6 * threadIdx.x + 2 * h];
-            v.y = s[6 * threadIdx.x + 2 * h + 1];
-            __builtin_nontemporal_store(v, d + h * N3);
-        }
+        for (int f = 0; f < 6; ++f)
+            __builtin_nontemporal_store(s[6 * threadIdx.x + f], dst + gp_index(e, f, p, N3));
     }
 }
 
@@ -372,22 +367,32 @@ extern "C" int nbx_repack_g_aos_to_soa(const double *g_aos, double *g_soa, int N
     return NBX_OK;
 }
 
+namespace nbx {
+
+int pair_factors_launch(const double *g6, double *g_pairs, int N, int64_t E, hipStream_t s)
+{
+    const int N3 = N * N * N;
+    const int64_t n3e = 3 * E * N3;
+    if (n3e == 0) return NBX_OK;
+    if ((n3e + 255) / 256 > 0x7fffffffLL) return NBX_EUNSUPPORTED;
+    hipLaunchKernelGGL(pair_factors_kernel, dim3((unsigned)((n3e + 255) / 256)), dim3(256), 0, s,
+                       n3e, N3, g6, g_pairs);
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+}  // namespace nbx
+
 extern "C" int nbx_pair_factors(const double *g6, double *g_pairs, int N, int64_t E,
                                 void *stream)
 {
     if (N < 2 || N > kMaxN || E < 0) return NBX_EINVAL;
     if (E == 0) return NBX_OK;
     if (!g6 || !g_pairs) return NBX_EINVAL;
-    const int N3 = N * N * N;
-    const int64_t n3e = 3 * E * N3;
-    if ((n3e + 255) / 256 > 0x7fffffffLL) return NBX_EUNSUPPORTED;
     const uintptr_t a = (uintptr_t)g6, b = (uintptr_t)g_pairs,
-                    bytes = (uintptr_t)(2 * n3e) * sizeof(double);
+                    bytes = (uintptr_t)(6 * E * (int64_t)N * N * N) * sizeof(double);
     if (a < b + bytes && b < a + bytes) return NBX_EINVAL;
-    hipLaunchKernelGGL(pair_factors_kernel, dim3((unsigned)((n3e + 255) / 256)), dim3(256), 0,
-                       as_stream(stream), n3e, N3, g6, g_pairs);
-    NBX_LAUNCH_CHECK();
-    return NBX_OK;
+    return pair_factors_launch(g6, g_pairs, N, E, as_stream(stream));
 }
 
 extern "C" int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host,

@@ -5,7 +5,10 @@
 #include "internal.hpp"
 
 struct nbx_problem {
+    // G: the problem's own copy of the caller's factors in factor pairs
+    // (g_index), the layout of the fused operator; D stays caller-owned.
     const double *G = nullptr, *D = nullptr;
+    double *Gown = nullptr;
     int N = 0;
     int64_t E = 0, n = 0;
     nbx_gs *gs = nullptr;

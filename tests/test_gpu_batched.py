@@ -160,6 +160,35 @@ def test_mixed_batched_breakdown_and_limit_are_per_problem():
         assert np.array_equal(host(x), host(xr))
 
 
+@pytest.mark.parametrize("case", ["max_outer", "stall"])
+def test_mixed_batched_host_ended_problems_stop_on_the_device(case):
+    """A mixed solve can end on the host while its device flag still reads
+    'continue': after max_outer residual replacements, or when two updates
+    in a row fail to cut the true residual fourfold (forced here with an
+    inner tolerance of 0.9, which then hands the solve to the FP64
+    fallback).  In a batch every later replay would keep iterating such a
+    problem; its iterations, updates, fallback and solution must still be
+    exactly those of its standalone solve."""
+    probs = _problems()[:4]
+    kw = dict(rtol=1e-10, max_iter=6000, check_every=10, prec=nbx.F32)
+    kw.update(max_outer=2) if case == "max_outer" else kw.update(inner_rtol=0.9)
+    refs = []
+    for _, st in probs:
+        x, r = st.problem.pcg(st.b, **kw)
+        refs.append((host(x), r.iters, r.outer_iters, r.fell_back, r.flag))
+    xs, res, _ = nbx.pcg_batched([st.problem for _, st in probs], [st.b for _, st in probs],
+                                 **kw)
+    for (xr, it, outer, fb, fl), x, r in zip(refs, xs, res):
+        print(f"{case}: standalone {it} it / {outer} updates / fell back {fb} / flag {fl}; "
+              f"batched {r.iters} / {r.outer_iters} / {r.fell_back} / {r.flag}")
+        assert (r.iters, r.outer_iters, r.fell_back, r.flag) == (it, outer, fb, fl)
+        assert np.array_equal(host(x), xr)
+    if case == "stall":
+        assert any(r.fell_back == 1 for r in res) and all(r.flag == 1 for r in res)
+    else:
+        assert all(r.outer_iters == 2 and r.flag == 0 for r in res)
+
+
 def test_mixed_batched_refuses_restarted_refinement():
     probs = _problems()[:2]
     with pytest.raises(nbx.NbxError):

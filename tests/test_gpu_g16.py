@@ -14,7 +14,6 @@ import pytest
 import oracle as O
 import synthetic as S
 from oracle import g16
-from layout import pairs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -54,7 +53,7 @@ def test_pack_bit_exact(fmt, N, E):
     G = _factors(E, N, seed=N)
     G[1] = 0.0                                         # an all-zero element
     words, gs = g16.pack(G, N, fmt)                   # [E, 6, N^3]
-    w_gpu, gs_gpu = nbx.g16_pack(cuda(pairs(G)), N, FMT[fmt])
+    w_gpu, gs_gpu = nbx.g16_pack(cuda(G), N, FMT[fmt])
     assert np.array_equal(host(gs_gpu), gs)
     # the library stores factor pairs (g1,g2), (g3,g4), (g5,g6) per node
     want = words.reshape(E, 3, 2, N ** 3).transpose(0, 1, 3, 2)
@@ -70,7 +69,7 @@ def test_ax_g16_matches_fp32_oracle(fmt, N, E):
     words, gs = g16.pack(G, N, fmt)
     Gd = g16.unpack(words, gs, N, fmt)                 # exactly representable in FP32
     want = O.ax_f32(u, Gd.astype(np.float32), O.deriv(N))
-    G16, gsc = nbx.g16_pack(cuda(pairs(G)), N, FMT[fmt])
+    G16, gsc = nbx.g16_pack(cuda(G), N, FMT[fmt])
     got = host(nbx.ax_g16(cuda(u, torch.float32), G16, gsc, nbx.deriv_device(N), FMT[fmt]))
     for e in range(E):                                 # elements span twelve decades
         err = rel(got[e], want[e])
@@ -84,7 +83,7 @@ def test_ax_g16_matches_fp32_oracle(fmt, N, E):
 
 def test_g16_argument_errors():
     N, E = 4, 2
-    G = cuda(pairs(_factors(E, N, 1)))
+    G = cuda(_factors(E, N, 1))
     with pytest.raises(nbx.NbxError):
         nbx.g16_pack(G, N, nbx.F32)                    # not a 16-bit format
     G16, gs = nbx.g16_pack(G, N, nbx.F16)

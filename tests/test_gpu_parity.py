@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synthetic as S
-from layout import pairs, planes
+from layout import pairs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,8 +57,11 @@ def test_ax_random_factors(N, E):
     u = S.uniform_field(E, N, seed=N)
     G = S.random_factors(E, N, seed=N + 1)
     want = O.ax(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u), cuda(pairs(G)), nbx.deriv_device(N)))
+    D = nbx.deriv_device(N)
+    got = host(nbx.ax(cuda(u), cuda(G), D))            # [E, 6, N^3], the contract
     assert_rel(got, want, TOL)
+    # the factor-pair fast path computes the same bits
+    assert np.array_equal(host(nbx.ax_paired(cuda(u), cuda(pairs(G)), D)), got)
 
 
 def test_ax_zero_elements_is_noop():
@@ -81,7 +84,8 @@ def test_geometry_and_ax_on_deformed_mesh(dims, N):
     b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
     P = O.setup(b)
     G, bm, xyz = nbx.geom_brick(*dims, N, b.deform_array(), with_xyz=True)
-    assert_rel(planes(host(G), N ** 3), P.G, TOL)
+    assert tuple(G.shape) == (b.E, 6, N ** 3)
+    assert_rel(host(G), P.G, TOL)
     assert_rel(host(bm), P.bm, TOL)
     assert_rel(host(xyz)[0], P.x, 1e-15)
     u = S.uniform_field(b.E, N, seed=3)
@@ -96,8 +100,10 @@ def test_ax_full_size_seeded_factors():
     print("ax parity at E=32768 N=10 (seeded factors)", flush=True)
     u = S.uniform_field(E, N, seed=0)
     G = S.random_factors(E, N, seed=1)
-    w = nbx.ax(cuda(u), cuda(pairs(G)), nbx.deriv_device(N))
-    assert_rel(host(w), O.ax(u, G, O.deriv(N)), TOL)
+    D = nbx.deriv_device(N)
+    w = host(nbx.ax(cuda(u), cuda(G), D))
+    assert_rel(w, O.ax(u, G, O.deriv(N)), TOL)
+    assert np.array_equal(host(nbx.ax_paired(cuda(u), cuda(pairs(G)), D)), w)
 
 
 def test_ax_full_size_deformed_c2():
@@ -115,7 +121,7 @@ def test_ax_full_size_deformed_c2():
     x, y, z = O.brick_coords(b, xi)
     Go, bmo, _ = O.geom(N, D, wq, x, y, z)
     del x, y, z
-    assert_rel(planes(host(G), N ** 3), Go, TOL)
+    assert_rel(host(G), Go, TOL)
     assert_rel(host(bm), bmo, TOL)
     u = S.uniform_field(b.E, N, seed=0)
     w = nbx.ax(cuda(u), G, nbx.deriv_device(N))
@@ -124,7 +130,7 @@ def test_ax_full_size_deformed_c2():
 
 def test_ax_is_deterministic():
     N, E = 10, 300
-    u = cuda(S.uniform_field(E, N, 5)); G = cuda(pairs(S.random_factors(E, N, 6)))
+    u = cuda(S.uniform_field(E, N, 5)); G = cuda(S.random_factors(E, N, 6))
     D = nbx.deriv_device(N)
     a = host(nbx.ax(u, G, D)); b = host(nbx.ax(u, G, D))
     assert np.array_equal(a, b)
@@ -138,8 +144,7 @@ def test_ax_fp32_error_vs_oracle(N):
     u = S.uniform_field(E, N, seed=11)
     G = S.random_factors(E, N, seed=12)
     want = O.ax(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u, torch.float32), cuda(pairs(G), torch.float32),
-                      nbx.deriv_device(N)))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
     err = rel(got, want)
     print(f"fp32 AX N={N}: normwise error {err:.3e}")
     assert err <= 300 * np.finfo(np.float32).eps
@@ -299,7 +304,7 @@ def test_every_tile_is_bit_identical(N, E):
     """The autotuner's search space: every elements-per-workgroup choice
     that fits computes the same bits (including the ragged last block)."""
     G6 = S.random_factors(E, N, seed=32)
-    u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(pairs(G6))
+    u = cuda(S.uniform_field(E, N, seed=31)); G = cuda(G6); Gp = cuda(pairs(G6))
     D = nbx.deriv_device(N)
     ref = None
     for epb in (1, 2, 4, 8):
@@ -313,6 +318,7 @@ def test_every_tile_is_bit_identical(N, E):
             assert_rel(w, O.ax(host(u), G6, O.deriv(N)), TOL)
         else:
             assert np.array_equal(w, ref), epb
+        assert np.array_equal(host(nbx.ax_paired(u, Gp, D, epb=epb)), ref), epb
 
 
 def test_tile_table_roundtrip():
@@ -332,8 +338,7 @@ def test_ax_fp32_matches_oracle_fp32(N):
     u = S.uniform_field(E, N, seed=41).astype(np.float32)
     G = S.random_factors(E, N, seed=42).astype(np.float32)
     want = O.ax_f32(u, G, O.deriv(N))
-    got = host(nbx.ax(cuda(u, torch.float32), cuda(pairs(G), torch.float32),
-                      nbx.deriv_device(N)))
+    got = host(nbx.ax(cuda(u, torch.float32), cuda(G, torch.float32), nbx.deriv_device(N)))
     assert_rel(got, want, 16 * N * np.finfo(np.float32).eps)
 
 
@@ -416,6 +421,20 @@ def test_binding_refuses_mis_sized_tensors():
                out=short)
     with pytest.raises(ValueError):
         nbx.ax(torch.zeros((st.E, st.N ** 3), dtype=torch.float64, device=DEV), st.G[:1], st.D)
+    # the contract's [E, 6, N^3] factors and the pair layout are not
+    # interchangeable: each entry point refuses the other's shape
+    u0 = torch.zeros((st.E, st.N ** 3), dtype=torch.float64, device=DEV)
+    Gp = nbx.pair_factors(st.G, st.N)
+    with pytest.raises(ValueError):
+        nbx.ax(u0, Gp, st.D)
+    with pytest.raises(ValueError):
+        nbx.ax_paired(u0, st.G, st.D)
+    # a contiguous view that does not start on a 16-byte boundary
+    buf = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        st.problem.pcg(st.b, x=buf[1:])
+    with pytest.raises(ValueError):
+        nbx.ax(buf[1:].view(st.E, -1), st.G, st.D)
     net = nbx.Mlp(st.N ** 3 + 6, 64, st.N ** 3, max_batch=64)
     with pytest.raises(ValueError):
         net.forward(torch.zeros((64, 8), dtype=torch.bfloat16, device=DEV))
@@ -499,26 +518,30 @@ def test_indefinite_operator_reports_breakdown(prec):
 @pytest.mark.parametrize("N,E", [(2, 1), (3, 7), (10, 33), (16, 3)])
 def test_factor_layout_conversions(N, E):
     """nbx_repack_g_aos_to_soa (from the layout of the operator's g
-    argument, g(6, N^3, E) with the factor fastest) and nbx_pair_factors
-    (from one plane per factor) into the library's planes of factor pairs,
-    bit for bit (node counts below, at and off the kernels' 256-node
-    blocks); AX agrees on the converted factors."""
+    argument, g(6, N^3, E) with the factor fastest) into one plane per
+    factor, and nbx_pair_factors from planes into factor pairs, bit for bit
+    (node counts below, at and off the kernels' 256-node blocks); AX agrees
+    on the converted factors."""
     G6 = S.random_factors(E, N, seed=41)                 # [E, 6, N^3]
-    want = cuda(pairs(G6))                               # [E, 3, N^3, 2]
+    want = cuda(G6)
+    wantp = cuda(pairs(G6))                              # [E, 3, N^3, 2]
     aos = cuda(G6.transpose(0, 2, 1))                    # [E, N^3, 6]
     assert torch.equal(nbx.repack_g_aos_to_soa(aos, N), want)
-    assert torch.equal(nbx.pair_factors(cuda(G6), N), want)
+    assert torch.equal(nbx.pair_factors(cuda(G6), N), wantp)
     out = torch.full_like(want, float("nan"))
     nbx.repack_g_aos_to_soa(aos, N, out=out)
     assert torch.equal(out, want)
     with pytest.raises(nbx.NbxError):                    # overlapping arrays
         nbx.repack_g_aos_to_soa(aos, N, out=aos)
     with pytest.raises(nbx.NbxError):
-        nbx.pair_factors(want, N, out=want)
+        nbx.pair_factors(wantp, N, out=wantp)
     empty = torch.empty((0, N ** 3, 6), dtype=torch.float64, device=DEV)
-    assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 3, N ** 3, 2)
+    assert nbx.repack_g_aos_to_soa(empty, N).shape == (0, 6, N ** 3)
     u = S.uniform_field(E, N, seed=42)
-    assert_rel(host(nbx.ax(cuda(u), want, nbx.deriv_device(N))), O.ax(u, G6, O.deriv(N)), TOL)
+    D = nbx.deriv_device(N)
+    w = host(nbx.ax(cuda(u), nbx.repack_g_aos_to_soa(aos, N), D))
+    assert_rel(w, O.ax(u, G6, O.deriv(N)), TOL)
+    assert np.array_equal(host(nbx.ax_paired(cuda(u), wantp, D)), w)
 
 
 @pytest.mark.parametrize("N", [11, 13, 16])

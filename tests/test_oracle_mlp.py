@@ -122,18 +122,3 @@ def test_fpcg_detects_breakdown():
     with pytest.raises(M.FpcgBreakdown) as ei:
         M.fpcg(P.apply_A, flip, P.b, P.c, max_iter=50)
     assert ei.value.iteration == 1
-
-
-def test_learned_preconditioner_with_zero_network_is_jacobi():
-    b = S.Brick(2, 2, 2, 6, ((0.05, 2, 2, 2),) * 3)
-    P = O.setup(b)
-    shape = M.Shape(6 ** 3 + 6, 64, 6 ** 3)
-    gfeat, gd = M.element_features(P.G, 6)
-    r = S.uniform_field(b.E, 6, seed=2).reshape(-1) * (1 - P.bnd)
-    z = M.apply_learned(P, shape, np.zeros(shape.n_params), r, gfeat, gd)
-    np.testing.assert_array_equal(z, P.dinv * r)
-    # affine cube elements: normalised diagonal factors are 1, cross ones 0
-    Pa = O.setup(S.Brick(2, 2, 2, 4))
-    ga, _ = M.element_features(Pa.G, 4)
-    np.testing.assert_allclose(ga[:, [0, 3, 5]], 1.0, rtol=1e-14)
-    np.testing.assert_allclose(ga[:, [1, 2, 4]], 0.0, atol=1e-15)
