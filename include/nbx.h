@@ -280,6 +280,29 @@ int nbx_problem_dinv(nbx_problem *p, double *out, void *stream);
 int nbx_pcg_iterate(nbx_problem *p, double *x, double *r, double *z, double *pdir,
                     double *scal, int n_iter, void *stream);
 
+/* Partial sums that nbx_pcg_iterate_noalloc can hold: one per workgroup
+ * of the fused first stage, ceil(E / tile) with the FP64 tile of
+ * nbx_pcg_get_tile (4 MB of device memory per GPU in all). */
+#define NBX_NOALLOC_MAX_BLOCKS 262144
+
+/* nbx_pcg_iterate without a problem handle and without any allocation, for
+ * callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid it.  The caller passes
+ * everything the iterations read and write: the factors as factor pairs
+ * Gp[E][3][N^3][2] (nbx_pair_factors), D, a plan gs for E N^3 local nodes,
+ * dinv (e.g. from nbx_jacobi_setup), the state x, r, z, pdir and scal as
+ * for nbx_pcg_iterate, and w[E][N^3], which receives A p of the last step.
+ * The reduction partials live in a fixed device array per GPU (looked up on
+ * the first call on each device): every call on one GPU shares it, so calls
+ * that overlap on one GPU race; nothing needs clearing between calls.
+ * Same kernels, order and results as nbx_pcg_iterate.  Async; allocates
+ * nothing and calls no allocating routine.  NBX_EINVAL for null pointers,
+ * N outside [2, 16], E < 1 or a plan of another size; NBX_EUNSUPPORTED if
+ * ceil(E / tile) exceeds NBX_NOALLOC_MAX_BLOCKS. */
+int nbx_pcg_iterate_noalloc(const double *Gp, const double *D, int N, int64_t E, nbx_gs *gs,
+                            const double *dinv, double *x, double *r, double *z, double *pdir,
+                            double *w, double *scal, int n_iter, void *stream);
+
 typedef struct {
     int max_iter;        /* iteration cap (default 1000) */
     int fixed_iters;     /* nonzero: run exactly max_iter iterations, no test */

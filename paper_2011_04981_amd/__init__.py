@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libnbx.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 SCAL_LEN = 16
+NOALLOC_MAX_BLOCKS = 262144   # partial sums nbx_pcg_iterate_noalloc can hold
 S_RHO, S_BETA, S_ALPHA, S_PAP, S_RR, S_BB, S_STOP, S_FLAG, S_ITER, S_MAXIT = range(10)
 
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "unsupported",
@@ -91,6 +92,8 @@ def lib():
         "nbx_repack_g_aos_to_soa": ([vp, vp, i32, i64, vp], i32),
         "nbx_pair_factors": ([vp, vp, i32, i64, vp], i32),
         "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
+        "nbx_pcg_iterate_noalloc": ([vp, vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32,
+                                     vp], i32),
         "nbx_pcg_default_opts": ([C.POINTER(PcgOpts)], None),
         "nbx_pcg": ([vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgResult), vp], i32),
         "nbx_pcg_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32,
@@ -546,6 +549,27 @@ class Problem:
                                      _dptr(z, torch.float64), _dptr(p, torch.float64),
                                      _dptr(scal, torch.float64), n_iter, _stream(stream)),
                "nbx_pcg_iterate")
+
+
+def pcg_iterate_noalloc(Gp, D, N: int, gs: GS, dinv, x, r, z, p, w, scal, n_iter: int,
+                        stream=None):
+    """nbx_pcg_iterate_noalloc: FP64 Jacobi-PCG iterations on caller state
+    with factor pairs Gp [E, 3, N^3, 2]; the library allocates nothing."""
+    torch = _torch()
+    E = Gp.shape[0]
+    if tuple(Gp.shape) != (E, 3, N ** 3, 2):
+        raise ValueError(f"Gp must be shaped (E, 3, {N ** 3}, 2)")
+    n = E * N ** 3
+    _need(D, N * N, "D")
+    for t, nm in ((dinv, "dinv"), (x, "x"), (r, "r"), (z, "z"), (p, "p"), (w, "w")):
+        _need(t, n, nm)
+    _need(scal, SCAL_LEN, "scal")
+    f = torch.float64
+    _check(lib().nbx_pcg_iterate_noalloc(_dptr(Gp, f, "Gp"), _dptr(D, f, "D"), N, E, gs.handle,
+                                         _dptr(dinv, f, "dinv"), _dptr(x, f, "x"),
+                                         _dptr(r, f, "r"), _dptr(z, f, "z"), _dptr(p, f, "p"),
+                                         _dptr(w, f, "w"), _dptr(scal, f, "scal"), n_iter,
+                                         _stream(stream)), "nbx_pcg_iterate_noalloc")
 
 
 def ax_flops(N: int, E: int) -> int:

@@ -18,6 +18,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 namespace nbx {
@@ -226,6 +227,61 @@ extern "C" int nbx_pcg_iterate(nbx_problem *P, double *x, double *r, double *z, 
 {
     if (!P || !x || !r || !z || !pdir || !scal || n_iter < 0) return NBX_EINVAL;
     return enqueue_iters(P, x, r, z, pdir, scal, n_iter, as_stream(stream));
+}
+
+// ------------------------------------------ the allocation-free variant
+//
+// For callers that cannot allocate (code under stream capture, serving
+// loops): the reduction partials of nbx_pcg_iterate_noalloc live in one
+// file-scope device array per GPU, reached through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in in host code).  Every call on a GPU shares that GPU's
+// array, so calls that overlap on one GPU race.  Each launch writes every
+// partial it later reads, so nothing needs clearing between calls.
+namespace {
+
+constexpr int64_t kNoallocPart3 = 2 * (int64_t)sk::kMaxRedBlocks;   // 2 MB
+constexpr int64_t kNoallocPart1 = NBX_NOALLOC_MAX_BLOCKS;           // 2 MB
+__device__ __align__(256) double scratch[kNoallocPart3 + kNoallocPart1];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up once per device).
+int scratch_for_current_device(double **out)
+{
+    int dev = 0;
+    NBX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return NBX_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        NBX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return NBX_OK;
+}
+
+}  // namespace
+
+extern "C" int nbx_pcg_iterate_noalloc(const double *Gp, const double *D, int N, int64_t E,
+                                       nbx_gs *gs, const double *dinv, double *x, double *r,
+                                       double *z, double *pdir, double *w, double *scal,
+                                       int n_iter, void *stream)
+{
+    if (!Gp || !D || !gs || !dinv || !x || !r || !z || !pdir || !w || !scal || n_iter < 0)
+        return NBX_EINVAL;
+    if (N < 2 || N > kMaxN || E < 1) return NBX_EINVAL;
+    const int64_t n = E * (int64_t)N * N * N;
+    if (gs->plan.n_local != n) return NBX_EINVAL;
+    if (ax_blocks(NBX_F64, N, E) > kNoallocPart1) return NBX_EUNSUPPORTED;   // scratch too small
+    double *sc = nullptr;
+    const int st = scratch_for_current_device(&sc);
+    if (st != NBX_OK) return st;
+    const IterArgs a{Gp, D, dinv, N, E, n, &gs->plan, w, sc + kNoallocPart3, sc};
+    return enqueue_iters_on(a, x, r, z, pdir, scal, n_iter, as_stream(stream));
 }
 
 extern "C" void nbx_pcg_default_opts(nbx_pcg_opts *o)
