@@ -251,6 +251,10 @@ def main():
             G16b, gsb = nbx.g16_pack(G, N, nbx.BF16)
             runs["g_fp16"] = (lambda: nbx.ax_g16(u32, G16f, gsf, D, nbx.F16, out=w32), 20)
             runs["g_bf16"] = (lambda: nbx.ax_g16(u32, G16b, gsb, D, nbx.BF16, out=w32), 20)
+            # the same operators on matrix cores (FP32 products and accumulation)
+            runs["mfma_fp32"] = (lambda: nbx.ax_mfma(u32, G32, D, out=w32), 32)
+            runs["mfma_g_fp16"] = (lambda: nbx.ax_mfma(u32, G16f, D, gprec=nbx.F16, gscale=gsf,
+                                                       out=w32), 20)
         for name, (fn, bpn) in runs.items():
             for _ in range(50):
                 fn()
@@ -377,6 +381,10 @@ def main():
                         "mixed_fp32_restarted": dict(prec=nbx.F32, mixed_mode=1,
                                                      inner_rtol=1e-5),
                         "mixed_f16_storage": dict(prec=nbx.F16, mixed_mode=0, inner_rtol=0.1),
+                        "mixed_fp32_mfma": dict(prec=nbx.F32, mixed_mode=0, inner_rtol=0.1,
+                                                inner_mfma=1),
+                        "mixed_f16_storage_mfma": dict(prec=nbx.F16, mixed_mode=0,
+                                                       inner_rtol=0.1, inner_mfma=1),
                         "mixed_bf16_storage": dict(prec=nbx.BF16, mixed_mode=0,
                                                    inner_rtol=0.1)}
             for name, kw in variants.items():
@@ -395,7 +403,9 @@ def main():
                                  "speedup_vs_fp64": round(pcg["fp64"]["seconds"] / min(times),
                                                           3),
                                  "inner": {nbx.F32: "fp32", nbx.F16: "G in fp16, fp32 vectors",
-                                           nbx.BF16: "G in bf16, fp32 vectors"}[kw["prec"]],
+                                           nbx.BF16: "G in bf16, fp32 vectors"}[kw["prec"]]
+                                          + (", operator on matrix cores"
+                                             if kw.get("inner_mfma") else ""),
                                  "mixed_mode": kw["mixed_mode"],
                                  "inner_rtol": kw["inner_rtol"]}
                     log(f"{name}: {rm.iters} it / {rm.outer_iters} outer, {min(times):.4f} s")

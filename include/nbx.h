@@ -198,6 +198,19 @@ int nbx_g16_pack(int gprec, const double *G, int N, int64_t E, void *G16, float 
 int nbx_ax_g16(int gprec, const float *u, const void *G16, const float *gscale,
                const double *D, int N, int64_t E, float *w, void *stream);
 
+/* The FP32 operator on matrix cores, the reduced-precision option of the
+ * inner iterations: per element, the six length-N contractions are
+ * 16x16x4 FP32 matrix-core products of D (or D^T, N padded to 16) with the
+ * element's values arranged with the contracted index inside; one 64-lane
+ * workgroup per element, values staged in LDS.  gprec NBX_F32: G is FP32
+ * [E][6][N^3] (gscale unused, may be NULL); NBX_F16 / NBX_BF16: G16 and
+ * gscale from nbx_g16_pack.  u, w float [E][N^3].  FP32 products, FP32
+ * accumulation: the FP32 kernels' accuracy, not their bits.  Async; no
+ * allocation.  NBX_EINVAL for null pointers, N outside [2,16], E < 0,
+ * u == w; NBX_EUNSUPPORTED for another gprec. */
+int nbx_ax_mfma(int gprec, const float *u, const void *G, const float *gscale, const double *D,
+                int N, int64_t E, float *w, void *stream);
+
 /* ------------------------------------------------ gather-scatter (dssum) --
  * The "nearest-neighbour communication" step of a CG iteration (Section
  * II-B), on one GPU: local copies of a global node are summed and the sum
@@ -319,6 +332,10 @@ typedef struct {
     int max_outer;       /* cap on reliable updates / refinement steps */
     int mixed_mode;      /* 0: one FP32 Krylov sequence with FP64 reliable
                             updates; 1: restarted iterative refinement */
+    int inner_mfma;      /* nonzero: the FP32 iterations' operator on matrix
+                            cores (nbx_ax_mfma's kernel) instead of the
+                            vector-unit kernel; standalone solves only
+                            (nbx_pcg_batched returns NBX_EUNSUPPORTED) */
 } nbx_pcg_opts;
 
 typedef struct {

@@ -229,14 +229,15 @@ def exact_params(shape: Shape, A_ref: np.ndarray, gd_ref: float):
                        np.zeros((shape.K, h)), softplus_inv(lam)])
 
 
-def loss_and_grad_bf16(shape: Shape, params, X, T, F):
+def loss_and_grad_bf16(shape: Shape, params, X, T, F, rnd=None):
     """loss_and_grad with the library's bfloat16 operand roundings: the
     products take X, F, L, the perceptron's weights and hidden activations,
     Q = Hx * gamma, the output gradient dZ, gamma * Pm and the perceptron's
     back-propagated gradients rounded to bfloat16 (FP64 accumulation here,
     FP32 in the library); bias gradients sum the unrounded dA and the
-    rounded hidden gradients, as the library's column sums do."""
-    r = bf16_round
+    rounded hidden gradients, as the library's column sums do.  rnd
+    replaces the rounding (the identity gives loss_and_grad back)."""
+    r = bf16_round if rnd is None else rnd
     L, W1, b1, W2, b2, W3, b3 = shape.unpack(params)
     Xr, Fr, Lr = r(X), r(F), r(L)
     W1r, W2r, W3r = r(W1), r(W2), r(W3)

@@ -163,3 +163,36 @@ def fpcg(apply_A, precond, b, c, x0=None, max_iter=1000, rtol=1e-10, on_step=Non
         beta = -dot(z, w) / pw
         p = z + beta * p
     return x, max_iter, np.array(hist)
+
+
+def loss_and_grad_bf16(shape: Shape, params, X, T, rnd=None):
+    """loss_and_grad (and the output) with the library's bfloat16 rounding
+    points: the products take X, the weights, the hidden activations, the
+    output gradient and the back-propagated hidden gradients rounded to
+    bfloat16 (FP64 accumulation here, FP32 in the library); bias gradients
+    sum the unrounded output gradient and the rounded hidden ones, as the
+    library's column sums do.  Returns (loss, gradient arena, Y).  rnd
+    replaces the rounding (the identity gives loss_and_grad back)."""
+    r = bf16_round if rnd is None else rnd
+    W1, b1, W2, b2, W3, b3 = shape.unpack(params)
+    Xr = r(X)
+    W1r, W2r, W3r = r(W1), r(W2), r(W3)
+    T = np.asarray(T, dtype=np.float64)
+    B = Xr.shape[0]
+    H1 = r(relu(Xr @ W1r.T + b1))
+    H2 = r(relu(H1 @ W2r.T + b2))
+    Y = H2 @ W3r.T + b3
+    D = np.zeros_like(Y)
+    D[:, :shape.n_out] = Y[:, :shape.n_out] - T[:, :shape.n_out]
+    loss = float(np.sum(D ** 2) / (B * shape.n_out))
+    dY = 2.0 * D / (B * shape.n_out)
+    dYr = r(dY)
+    dW3 = dYr.T @ H2
+    db3 = dY.sum(axis=0)
+    dH2 = r((dYr @ W3r) * (H2 > 0))
+    dW2 = dH2.T @ H1
+    db2 = dH2.sum(axis=0)
+    dH1 = r((dH2 @ W2r) * (H1 > 0))
+    dW1 = dH1.T @ Xr
+    db1 = dH1.sum(axis=0)
+    return loss, shape.pack([dW1, db1, dW2, db2, dW3, db3]), Y

@@ -41,7 +41,7 @@ class PcgOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("fixed_iters", C.c_int), ("check_every", C.c_int),
                 ("use_graph", C.c_int), ("rtol", C.c_double), ("prec", C.c_int),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int),
-                ("mixed_mode", C.c_int)]
+                ("mixed_mode", C.c_int), ("inner_mfma", C.c_int)]
 
 
 class PcgResult(C.Structure):
@@ -109,6 +109,7 @@ def lib():
         "nbx_mlp_train_step": ([vp, vp, vp, i32, C.c_float, vp, vp], i32),
         "nbx_g16_pack": ([i32, vp, i32, i64, vp, vp, vp], i32),
         "nbx_ax_g16": ([i32, vp, vp, vp, vp, i32, i64, vp, vp], i32),
+        "nbx_ax_mfma": ([i32, vp, vp, vp, vp, i32, i64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -364,6 +365,29 @@ def ax_g16(u, G16, gscale, D, gprec: int, out=None, stream=None):
     _check(lib().nbx_ax_g16(gprec, _dptr(u, torch.float32, "u"), _dptr(G16, torch.int16, "G16"),
                             _dptr(gscale, torch.float32, "gscale"), _dptr(D, torch.float64, "D"),
                             N, E, _dptr(w, torch.float32, "w"), _stream(stream)), "nbx_ax_g16")
+    return w
+
+
+def ax_mfma(u, G, D, gprec: int = F32, gscale=None, out=None, stream=None):
+    """w = AX(u) in FP32 on matrix cores (nbx_ax_mfma): G float32
+    [E, 6, N^3] for gprec F32, or 16-bit words from g16_pack with gscale."""
+    torch = _torch()
+    N = D.shape[0]
+    E = u.numel() // N ** 3
+    _need(u, E * N ** 3, "u")
+    _need(D, N * N, "D")
+    if gprec == F32:
+        if tuple(G.shape) != (E, 6, N ** 3) or G.dtype != torch.float32:
+            raise ValueError(f"G must be float32 shaped (E, 6, {N ** 3})")
+        gp, sp = _dptr(G, torch.float32, "G"), None
+    else:
+        if G.numel() != 6 * E * N ** 3 or gscale is None or gscale.numel() != E:
+            raise ValueError("G16 [E, 3, N^3, 2] and gscale [E] must match u")
+        gp, sp = _dptr(G, torch.int16, "G16"), _dptr(gscale, torch.float32, "gscale")
+    w = torch.empty_like(u) if out is None else _need(out, u.numel(), "out")
+    _check(lib().nbx_ax_mfma(gprec, _dptr(u, torch.float32, "u"), gp, sp,
+                             _dptr(D, torch.float64, "D"), N, E, _dptr(w, torch.float32, "w"),
+                             _stream(stream)), "nbx_ax_mfma")
     return w
 
 

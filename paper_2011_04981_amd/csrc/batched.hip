@@ -529,6 +529,7 @@ extern "C" int nbx_pcg_batched(nbx_problem *const *probs, const double *const *b
     if (o.max_iter < 0 || !(o.rtol >= 0) || o.max_outer < 1) return NBX_EINVAL;
     for (int p = 0; p < nprob; ++p)
         if (!probs[p] || !b[p] || !x[p]) return NBX_EINVAL;
+    if (o.inner_mfma) return NBX_EUNSUPPORTED;
     if (o.prec == NBX_F32 || o.prec == NBX_F16 || o.prec == NBX_BF16)
         return pcg_batched_mixed(probs, b, x, nprob, o, results, solve_seconds,
                                  as_stream(stream));

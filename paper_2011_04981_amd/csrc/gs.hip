@@ -62,13 +62,66 @@ void *dev_upload(const std::vector<T> &h, int &st)
     return p;
 }
 
+template <typename T>
+int dev_download(const T *d, size_t count, std::vector<T> &h)
+{
+    h.resize(count);
+    if (count == 0) return NBX_OK;
+    NBX_HIP(hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost));
+    return NBX_OK;
+}
+
+}  // namespace
+
 void free_plan(GsPlan &p)
 {
     hipFree(p.off); hipFree(p.idx); hipFree(p.gflag); hipFree(p.mask_idx); hipFree(p.info);
     p = GsPlan{};
 }
 
-}  // namespace
+int xpair_plan(const GsPlan &full, int64_t xd, GsPlan &out, int *found)
+{
+    *found = 0;
+    out = GsPlan{};
+    if (xd <= 0 || full.n_groups == 0) return NBX_OK;
+    std::vector<int32_t> off, idx, mask_idx;
+    std::vector<uint8_t> gflag, info;
+    int st = dev_download(full.off, (size_t)full.n_groups + 1, off);
+    if (st == NBX_OK) st = dev_download(full.idx, (size_t)off.back(), idx);
+    if (st == NBX_OK) st = dev_download(full.gflag, (size_t)full.n_groups, gflag);
+    if (st == NBX_OK) st = dev_download(full.mask_idx, (size_t)full.n_mask_only, mask_idx);
+    if (st == NBX_OK) st = dev_download(full.info, (size_t)full.n_local, info);
+    if (st != NBX_OK) return st;
+    for (uint8_t v : info)
+        if ((v & 0x7f) > kXpMult) return NBX_OK;   // the bits are needed for multiplicity
+    std::vector<int32_t> roff{0}, ridx;
+    std::vector<uint8_t> rflag;
+    int64_t pairs = 0;
+    for (int32_t g = 0; g < full.n_groups; ++g) {
+        const int32_t b = off[g], e = off[g + 1];
+        if (e - b == 2 && !gflag[g] && (int64_t)idx[b + 1] - idx[b] == xd) {
+            info[idx[b]] = (uint8_t)((info[idx[b]] & kXpMult) | kXpNext);
+            info[idx[b + 1]] = (uint8_t)((info[idx[b + 1]] & kXpMult) | kXpPrev);
+            ++pairs;
+            continue;
+        }
+        ridx.insert(ridx.end(), idx.begin() + b, idx.begin() + e);
+        roff.push_back((int32_t)ridx.size());
+        rflag.push_back(gflag[g]);
+    }
+    if (pairs == 0) return NBX_OK;
+    out.n_local = full.n_local;
+    out.n_groups = (int32_t)rflag.size();
+    out.n_mask_only = full.n_mask_only;
+    out.off = (int32_t *)dev_upload(roff, st);
+    if (st == NBX_OK) out.idx = (int32_t *)dev_upload(ridx, st);
+    if (st == NBX_OK) out.gflag = (uint8_t *)dev_upload(rflag, st);
+    if (st == NBX_OK) out.mask_idx = (int32_t *)dev_upload(mask_idx, st);
+    if (st == NBX_OK) out.info = (uint8_t *)dev_upload(info, st);
+    if (st != NBX_OK) { free_plan(out); return st; }
+    *found = 1;
+    return NBX_OK;
+}
 
 template <typename T>
 int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const double *flag)

@@ -61,6 +61,20 @@ struct GsPlan {
     uint8_t *info = nullptr;    // [n_local] bits 0..6 multiplicity, bit 7 Dirichlet
 };
 
+// The exchange plan of the solvers' iterations, derived from a full plan:
+// two-copy non-Dirichlet groups whose local indices are a and a + xd (for
+// the lexicographic element order, xd = N^3 - N + 1 pairs the last x-face
+// of an element with the first of the next one) leave the plan, and the
+// update kernel sums them from w instead, reading the pair's second value
+// from a line that its neighbourhood streams anyway.  The derived plan's
+// info byte carries the multiplicity in bits 0..4 (kXpMult), kXpNext at a,
+// kXpPrev at a + xd, and the Dirichlet bit 7.  Synchronous (reads the full
+// plan back); *found = 0, and nothing allocated, when no such pair exists or
+// a multiplicity exceeds kXpMult.
+constexpr uint8_t kXpMult = 0x1f, kXpNext = 0x20, kXpPrev = 0x40;
+int xpair_plan(const GsPlan &full, int64_t xd, GsPlan &out, int *found);
+void free_plan(GsPlan &p);
+
 // Enqueue dssum on a double or float vector.  With `flag` (device), the
 // kernels do nothing once *flag != 0 (a finished solve).
 template <typename T>
@@ -86,6 +100,15 @@ int ax_launch_g16(int gprec, const float *u, const void *G16, const float *gscal
 int ax_pcg_launch_g16(int gprec, const void *G16, const float *gscale, const double *D, int N,
                       int64_t E, const float *z, float *p, float *w, double *part,
                       const double *scal, hipStream_t s);
+// The FP32 operator on matrix cores (ax_mfma.hip): plain, on FP32 planes
+// (gprec NBX_F32) or 16-bit words (NBX_F16 / NBX_BF16 with gscale); fused
+// first stage on the problem's FP32 pairs or 16-bit words, one partial per
+// element.
+int ax_mfma_launch(int gprec, const float *u, const void *G, const float *gscale,
+                   const double *D, int N, int64_t E, float *w, hipStream_t s);
+int ax_mfma_pcg_launch(int gprec, const void *G, const float *gscale, const double *D, int N,
+                       int64_t E, const float *z, float *p, float *w, double *part,
+                       const double *scal, hipStream_t s);
 // Packs G (FP64, planes != 0: [E][6][N^3], else factor pairs) into the
 // 16-bit words and per-element scales of the reduced-storage operator.
 int g16_pack_launch(int gprec, int planes, const double *G, int N, int64_t E, void *G16,

@@ -51,13 +51,29 @@ unsigned grid_for(int64_t n)
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+// The inner operator's kernel choice as the captured graphs record it: the
+// fused-stage tile, or -1 for the matrix-core kernel.
+int inner_tile(const nbx_problem *P)
+{
+    return P->inner_mfma ? -1 : pcg_tile(P->inner_fmt, P->N);
+}
+
 int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
 {
-    const GsPlan &gs = P->gs->plan;
-    const int nb1 = ax_blocks(P->inner_fmt, P->N, P->E);   // the inner operator's tile
+    const GsPlan &gs = iter_plan(P);
+    // one partial per workgroup of the fused stage: per element on matrix cores
+    const int nb1 = P->inner_mfma ? (int)P->E : ax_blocks(P->inner_fmt, P->N, P->E);
     const int nb3 = sk::red_blocks(P->n, sk::Vec<float>::W);
     for (int it = 0; it < n_iter; ++it) {
-        int st = P->inner_fmt == NBX_F32
+        int st;
+        if (P->inner_mfma)
+            st = ax_mfma_pcg_launch(P->inner_fmt,
+                                    P->inner_fmt == NBX_F32 ? (const void *)P->G32
+                                                            : (const void *)P->G16,
+                                    P->gscale, P->D, P->N, P->E, P->z32, P->p32, P->w32,
+                                    P->part1, P->scal32, s);
+        else
+            st = P->inner_fmt == NBX_F32
                      ? ax_pcg_launch_f32(P->G32, P->D, P->N, P->E, P->z32, P->p32, P->w32,
                                          P->part1, P->scal32, s)
                      : ax_pcg_launch_g16(P->inner_fmt, P->G16, P->gscale, P->D, P->N, P->E,
@@ -67,9 +83,14 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
                            P->scal32);
         st = dssum_launch<float>(gs, P->w32, 1, s, P->scal32 + NBX_S_FLAG);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::update_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
-                           P->n, P->p32, P->w32, P->dinv32, gs.info, P->d32, P->r32, P->z32,
-                           P->part3, P->scal32);
+        if (P->xd)
+            hipLaunchKernelGGL(sk::update_xp_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0,
+                               s, P->n, P->p32, P->w32, P->dinv32, gs.info, P->d32, P->r32,
+                               P->z32, P->part3, P->scal32, P->xd);
+        else
+            hipLaunchKernelGGL(sk::update_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
+                               P->n, P->p32, P->w32, P->dinv32, gs.info, P->d32, P->r32,
+                               P->z32, P->part3, P->scal32);
         hipLaunchKernelGGL(sk::rr_reduce_kernel, dim3(1), dim3(1024), 0, s, nb3, P->part3,
                            P->scal32);
         NBX_LAUNCH_CHECK();
@@ -140,7 +161,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
     NBX_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 10;
     if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
-                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(P->inner_fmt, P->N))) {
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != inner_tile(P))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -154,7 +175,7 @@ static int inner_solve(nbx_problem *P, const nbx_pcg_opts &o, int max_iter, int 
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
-        P->g32_tile = pcg_tile(P->inner_fmt, P->N);
+        P->g32_tile = inner_tile(P);
     }
     int done = 0;
     while (true) {
@@ -185,6 +206,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
 int pcg_mixed(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts &o,
               nbx_pcg_result *res)
 {
+    P->inner_mfma = o.inner_mfma ? 1 : 0;
     return o.mixed_mode == 1 ? pcg_mixed_restart(P, b, x, o, res)
                              : pcg_mixed_reliable(P, b, x, o, res);
 }
@@ -413,7 +435,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
     if (st != NBX_OK) return st;
     const int chunk = o.check_every > 0 ? o.check_every : 10;
     if (o.use_graph && (P->gexec32 == nullptr || P->g32_iters != chunk ||
-                        P->g32_fmt != P->inner_fmt || P->g32_tile != pcg_tile(P->inner_fmt, P->N))) {
+                        P->g32_fmt != P->inner_fmt || P->g32_tile != inner_tile(P))) {
         if (P->gexec32) { hipGraphExecDestroy(P->gexec32); P->gexec32 = nullptr; }
         NBX_HIP(hipStreamSynchronize(s));
         NBX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -427,7 +449,7 @@ static int pcg_mixed_reliable(nbx_problem *P, const double *b, double *x,
         if (e != hipSuccess) { P->gexec32 = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
         P->g32_iters = chunk;
         P->g32_fmt = P->inner_fmt;
-        P->g32_tile = pcg_tile(P->inner_fmt, P->N);
+        P->g32_tile = inner_tile(P);
     }
     NBX_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();

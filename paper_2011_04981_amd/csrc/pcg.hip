@@ -30,12 +30,14 @@ int jacobi_setup_impl(const double *G, const double *D, int N, int64_t E, const 
 // pairs Gp, D, N, E), the exchange plan, dinv, the state vectors, w (A p of
 // the last step) and the two partial-sum buffers (part1: one double per
 // fused-stage workgroup, ax_blocks(); part3: 2 * red_blocks(n) doubles).
+// xd != 0: gs is an x-pair plan (xpair_plan) and K3 sums its pairs.
 struct IterArgs {
     const double *Gp, *D, *dinv;
     int N;
     int64_t E, n;
     const GsPlan *gs;
     double *w, *part1, *part3;
+    int64_t xd = 0;
 };
 
 // Enqueues n_iter fused FP64 iterations on s.
@@ -52,8 +54,12 @@ static int enqueue_iters_on(const IterArgs &a, double *x, double *r, double *z, 
                            scal);
         st = dssum_launch<double>(gs, a.w, 1, s, scal + NBX_S_FLAG);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::update_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
-                           a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal);
+        if (a.xd)
+            hipLaunchKernelGGL(sk::update_xp_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0,
+                               s, a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal, a.xd);
+        else
+            hipLaunchKernelGGL(sk::update_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
+                               a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal);
         hipLaunchKernelGGL(sk::rr_reduce_kernel, dim3(1), dim3(1024), 0, s, nb3, a.part3,
                            scal);
         NBX_LAUNCH_CHECK();
@@ -64,8 +70,8 @@ static int enqueue_iters_on(const IterArgs &a, double *x, double *r, double *z, 
 static int enqueue_iters(nbx_problem *P, double *x, double *r, double *z, double *p,
                          double *scal, int n_iter, hipStream_t s)
 {
-    const IterArgs a{P->G, P->D, P->dinv, P->N, P->E, P->n, &P->gs->plan,
-                     P->w, P->part1, P->part3};
+    const IterArgs a{P->G, P->D, P->dinv, P->N, P->E, P->n, &iter_plan(P),
+                     P->w, P->part1, P->part3, P->xd};
     return enqueue_iters_on(a, x, r, z, p, scal, n_iter, s);
 }
 
@@ -192,6 +198,11 @@ extern "C" int nbx_problem_create(const double *G, const double *D, int N, int64
     if (st != NBX_OK) return fail(st);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize"));
+    const int64_t xd = (int64_t)N * N * N - N + 1;
+    int found = 0;
+    st = xpair_plan(gs->plan, xd, P->xplan, &found);
+    if (st != NBX_OK) return fail(st);
+    if (found) P->xd = xd;
     *out = P;
     return NBX_OK;
 }
@@ -202,6 +213,7 @@ extern "C" int nbx_problem_destroy(nbx_problem *P)
     if (P->ws) hipStreamSynchronize(P->ws);
     if (P->gexec) hipGraphExecDestroy(P->gexec);
     if (P->gexec32) hipGraphExecDestroy(P->gexec32);
+    free_plan(P->xplan);
     hipFree(P->Gown);
     hipFree(P->dinv); hipFree(P->r); hipFree(P->z); hipFree(P->p); hipFree(P->w);
     hipFree(P->part1); hipFree(P->part3); hipFree(P->scal); hipFree(P->tmp2);
@@ -296,6 +308,7 @@ extern "C" void nbx_pcg_default_opts(nbx_pcg_opts *o)
     o->inner_rtol = 0.1;
     o->max_outer = 200;
     o->mixed_mode = 0;
+    o->inner_mfma = 0;
 }
 
 extern "C" int nbx_pcg(nbx_problem *P, const double *b, double *x, const nbx_pcg_opts *opts,

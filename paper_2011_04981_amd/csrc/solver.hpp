@@ -32,9 +32,21 @@ struct nbx_problem {
     float *gscale = nullptr;
     int g16_fmt = -1;                  // format G16 currently holds
     int inner_fmt = NBX_F32;           // operator the FP32 iterations use
+    int inner_mfma = 0;                // 1: the inner operator on matrix cores
+    // The solvers' exchange: the plan without the two-copy x-face groups,
+    // whose sums the update kernel forms from w, with their own info bytes
+    // (xplan.info, bits as sk::kXpNext / kXpPrev); xd = N^3 - N + 1, the
+    // local offset of an x-face pair; xd = 0 when the plan has no such
+    // pairs and the solvers use the full plan.
+    nbx::GsPlan xplan;
+    int64_t xd = 0;
 };
 
 namespace nbx {
+
+// The exchange plan of the solvers' iterations: xplan (with the x-face
+// pairs summed in the update kernel) when there is one, else the full plan.
+inline const GsPlan &iter_plan(const nbx_problem *P) { return P->xd ? P->xplan : P->gs->plan; }
 
 // FP64 residual r = b - mask(dssum(AX(x))) (r may be null) and
 // out[0] = <r,r>_c, out[1] = <b,b>_c; synchronous on s.

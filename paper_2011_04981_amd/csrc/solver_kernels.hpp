@@ -79,6 +79,9 @@ __device__ inline float fmaT(float a, float b, float c) { return __builtin_fmaf(
 // Per-node weight 1/multiplicity (info bits 0..6).
 __device__ inline double cw(uint8_t info) { return 1.0 / (double)(info & 0x7f); }
 
+// The same weight from the solvers' x-pair info byte (xpair_plan).
+__device__ inline double cw_x(uint8_t info) { return 1.0 / (double)(info & kXpMult); }
+
 // Workgroups for a vector kernel over n values, w values (one 16-byte
 // vector) per lane.
 inline int red_blocks(int64_t n, int w = 2)
@@ -193,14 +196,28 @@ template <> struct Vec<float> {
     static constexpr int W = 4;
 };
 
-// K3: x += alpha p; r -= alpha w; z = dinv r; partials of c r r and c r z.
-// Vector accesses of 16 bytes per lane, scalar tail.
+// The exchange of an x-face pair done inside K3: the assembled value of a
+// pair (a, a + xd) is the exchange's own sum, (0 + w[a]) + w[a + xd] with
+// the lower local index first, so the result has the same bits.
 template <typename T>
+__device__ __forceinline__ T xpair_w(T wl, uint8_t inf, const T *__restrict__ w, int64_t l,
+                                     int64_t xd)
+{
+    T s = 0;
+    if (inf & kXpNext) { s += wl; s += w[l + xd]; return s; }
+    if (inf & kXpPrev) { s += w[l - xd]; s += wl; return s; }
+    return wl;
+}
+
+// K3: x += alpha p; r -= alpha w; z = dinv r; partials of c r r and c r z.
+// Vector accesses of 16 bytes per lane, scalar tail.  With XP, info is the
+// solvers' xinfo and the x-face pairs are summed here (xpair_w).
+template <typename T, bool XP = false>
 __device__ __forceinline__ void
 update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
             const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
             T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
-            const double *__restrict__ scal, int64_t blk, int64_t nblk)
+            const double *__restrict__ scal, int64_t blk, int64_t nblk, int64_t xd = 0)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     using V = Vec<T>;
@@ -227,10 +244,13 @@ update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
         const typename V::iv inf = __builtin_nontemporal_load(iv + q);
 #pragma unroll
         for (int c = 0; c < W; ++c) {
+            const uint8_t ic = (uint8_t)(inf >> (8 * c));
+            T wc = wq[c];
+            if constexpr (XP) wc = xpair_w<T>(wc, ic, w, q * W + c, xd);
             xq[c] = fmaT(alpha, pq[c], xq[c]);
-            rq[c] = fmaT(-alpha, wq[c], rq[c]);
+            rq[c] = fmaT(-alpha, wc, rq[c]);
             zq[c] = dq[c] * rq[c];
-            const double cc = cw((uint8_t)(inf >> (8 * c)));
+            const double cc = XP ? cw_x(ic) : cw(ic);
             rr += cc * (double)rq[c] * (double)rq[c];
             rz += cc * (double)rq[c] * (double)zq[c];
         }
@@ -241,8 +261,10 @@ update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
     if (blk == 0 && threadIdx.x == 0) {
         for (int64_t l = nv * W; l < n; ++l) {
             x[l] = fmaT(alpha, p[l], x[l]);
-            const T rl = fmaT(-alpha, w[l], r[l]), zl = dinv[l] * rl;
-            const double cc = cw(info[l]);
+            T wl = w[l];
+            if constexpr (XP) wl = xpair_w<T>(wl, info[l], w, l, xd);
+            const T rl = fmaT(-alpha, wl, r[l]), zl = dinv[l] * rl;
+            const double cc = XP ? cw_x(info[l]) : cw(info[l]);
             r[l] = rl; z[l] = zl;
             rr += cc * (double)rl * (double)rl;
             rz += cc * (double)rl * (double)zl;
@@ -260,6 +282,16 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
               const double *__restrict__ scal)
 {
     update_body<T>(n, p, w, dinv, info, x, r, z, part, scal, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+update_xp_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
+                 const T *__restrict__ dinv, const uint8_t *__restrict__ info,
+                 T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
+                 double *__restrict__ part, const double *__restrict__ scal, int64_t xd)
+{
+    update_body<T, true>(n, p, w, dinv, info, x, r, z, part, scal, blockIdx.x, gridDim.x, xd);
 }
 
 // R3: rr, rho'; convergence / breakdown / iteration limit; beta.  With

@@ -158,7 +158,10 @@ def test_samples_match_reference():
     xb = M.bf16_bits(Xo)
     diff = np.abs(X[:b.E, :nI].astype(np.int32) - xb.astype(np.int32))
     assert diff.max() <= 1 and (diff > 0).mean() <= 1e-3      # rare rounding flips
-    assert np.array_equal(F[:b.E, :6], M.bf16_bits(Fo)) and np.all(F[:, 6:] == 0)
+    # features: each side's own geometry; cross-factor means near zero are
+    # rounding noise, so compare values (one bfloat16 ulp, or absolutely)
+    np.testing.assert_allclose(bf16_value(F[:b.E, :6]), Fo, rtol=2 ** -8, atol=1e-9)
+    assert np.all(F[:, 6:] == 0)
     assert np.all(X[b.E:] == 0) and np.all(T[b.E:] == 0) and np.all(F[b.E:] == 0)
 
 

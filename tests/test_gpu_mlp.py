@@ -98,6 +98,47 @@ def test_gradients_match_reference():
         assert err <= 5e-2, name
 
 
+def _close_but_for_flips(got, want, name):
+    """got agrees with the rounding-emulating reference but for bfloat16
+    rounding flips (an intermediate that lands within the FP32-vs-FP64
+    accumulation difference of a rounding boundary rounds the other way on
+    one side): the typical entry to 1e-6 of the block's scale, the block as
+    a whole to 2^-10 (a quarter of one bfloat16 rounding step) in the
+    Frobenius norm, every entry within 2e-3 (a flip moves one operand by
+    2^-8 of itself; a weight gradient entry sums many rows, so one flip
+    reaches a whole row of it, and the first layer's gradient, fed by the
+    flips of both hidden layers, measured 2.9e-4).  A reference without the
+    rounding points differs by percents."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    scale = max(np.abs(want).max(), 1e-300)
+    d = np.abs(got - want) / scale
+    fro = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    print(f"{name}: Frobenius {fro:.2e}, max {d.max():.2e}, median {np.median(d):.2e}")
+    assert np.median(d) <= 1e-6, name
+    assert fro <= 2.0 ** -10, name
+    assert d.max() <= 2e-3, name
+
+
+def test_forward_and_gradients_match_the_rounding_emulating_reference():
+    """The same network against a reference that rounds the library's
+    bfloat16 operands, hidden activations and back-propagated gradients:
+    forward and every gradient block agree but for rare rounding flips."""
+    shape, net, params, pr, X, T = _net(seed=7)
+    f32 = shape.pack([a.astype(np.float32).astype(np.float64) for a in shape.unpack(params)])
+    Xt = bf16_tensor(X)
+    Tt = torch.as_tensor(T, dtype=torch.float32).cuda()
+    Y = host(net.forward(Xt))
+    loss = host(net.grad(Xt, Tt))[0]
+    g = host(net.get_params(grads=True))
+    want_loss, want, want_Y = M.loss_and_grad_bf16(shape, f32, X, T)
+    _close_but_for_flips(Y[:, :shape.n_out], want_Y[:, :shape.n_out], "forward")
+    assert abs(loss - want_loss) <= 1e-5 * want_loss
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], shape.unpack(g),
+                          shape.unpack(want)):
+        _close_but_for_flips(a, b, f"grad {name}")
+
+
 def test_adam_first_step_and_training_reduces_loss():
     shape, net, params, pr, X, T = _net(seed=9)
     Xt = bf16_tensor(X)

@@ -213,7 +213,7 @@ def test_pcg_one_step_parity(case):
     st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
     state = O.pcg_start(P)
     done = 0
-    for k in (0, 1, 10, 50):
+    for k in (0, 1, 10, 50, 99):
         if k > done:
             x, r, z, p, rho, *_ = O.pcg_iterate(P, state, k - done)
             state = (x, r, z, p, rho)
@@ -284,19 +284,35 @@ def test_pcg_zero_rhs_returns_zero():
 
 
 def test_pcg_one_step_full_size_c2():
-    """One fused iteration on the full benchmark mesh from x = 0."""
+    """One fused iteration on the full benchmark mesh from the oracle's
+    state after k = 0 and k = 10 iterations, on identical inputs: the GPU
+    problem is built from the oracle's factors (its own geometry agrees to
+    1e-12, which AX turns into 1e-11, see the deformed-mesh AX test)."""
     b = S.c2_brick()
-    print("one-step parity at E=32768", flush=True)
     P = O.setup(b)
-    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
-    assert_rel(host(st.b), P.b, TOL)
+    ref = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    assert_rel(host(ref.b), P.b, TOL)
+    del ref
+
+    class St:
+        pass
+    st = St()
+    st.E, st.N = b.E, b.N
+    gid, bnd = nbx.brick_ids(b.ex, b.ey, b.ez, b.N)
+    gs = nbx.GS(gid, bnd)
+    st.problem = nbx.Problem(cuda(P.G), nbx.deriv_device(b.N), b.N, gs)
     state = O.pcg_start(P)
-    xs, rs, zs, ps, scal = _gpu_state(st, state[0], state[1], state[3], state[4])
-    st.problem.pcg_iterate(xs, rs, zs, ps, scal, 1)
-    x1, r1, z1, p1, rho1, *_ = O.pcg_iterate(P, state, 1)
-    assert_rel(host(xs), x1, TOL)
-    assert_rel(host(rs), r1, TOL)
-    assert abs(host(scal)[nbx.S_RHO] - rho1) <= TOL * abs(rho1)
+    for k in (0, 10):
+        print(f"one-step parity at E=32768, k={k}", flush=True)
+        if k:
+            state = O.pcg_iterate(P, state, k)[:5]
+        xs, rs, zs, ps, scal = _gpu_state(st, state[0], state[1], state[3], state[4])
+        st.problem.pcg_iterate(xs, rs, zs, ps, scal, 1)
+        x1, r1, z1, p1, rho1, *_ = O.pcg_iterate(P, state, 1)
+        assert_rel(host(xs), x1, TOL)
+        assert_rel(host(rs), r1, TOL)
+        assert_rel(host(zs), z1, TOL)
+        assert abs(host(scal)[nbx.S_RHO] - rho1) <= TOL * abs(rho1)
 
 
 @pytest.mark.parametrize("N,E", [(4, 37), (8, 9), (10, 131), (12, 5), (16, 3)])
@@ -467,6 +483,29 @@ def test_full_size_solves_checked_by_the_oracle_operator():
         assert rel_true <= 2e-10, (name, rel_true)
 
 
+def test_full_size_solves_at_n12_checked_by_the_oracle_operator():
+    """The C2 mapping at N = 12 (32^3 elements, 56.6 M local nodes), one of
+    the mixed-precision sweep's sizes: the FP64 solve and the FP16-stored
+    mixed solve to 1e-10, each solution's residual evaluated by the oracle
+    with its own geometry and operator."""
+    b = S.c2_brick(12)
+    print("full-size set-up at N=12 (oracle)", flush=True)
+    P = O.setup(b)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    bb = O.wdot(P.c, P.b, P.b)
+    for name, kw in (("fp64", dict(prec=nbx.F64)),
+                     ("f16", dict(prec=nbx.F16, inner_rtol=0.1))):
+        print(f"N=12 full-size solve {name}", flush=True)
+        x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=20000, check_every=20, **kw)
+        assert r.status == 0 and r.flag == 1, (name, r)
+        xh = host(x).reshape(-1)
+        res = P.b - P.apply_A(xh)
+        rel_true = np.sqrt(O.wdot(P.c, res, res) / bb)
+        print(f"{name}: {r.iters} it, oracle-operator relres {rel_true:.2e}")
+        assert rel_true <= 2e-10, (name, rel_true)
+        del x, xh, res
+
+
 @pytest.mark.parametrize("N", [2, 3])
 def test_pcg_tiny_elements(N):
     """Degenerate element orders: N = 2 (trilinear, no interior nodes) and
@@ -587,3 +626,34 @@ def test_mixed_solve_with_interior_shared_node(prec):
     print(f"{prec}: {r.iters} it, true relres {r.true_relres:.2e} (FP64 {r64.iters} it)")
     assert r64.status == 0 and r.status == 0 and r.true_relres <= 2e-10
     assert rel(host(x), host(x64)) <= 1e-8
+
+
+@pytest.mark.parametrize("dims,N", [((1, 3, 2), 4), ((5, 2, 3), 2), ((4, 3, 3), 7),
+                                    ((3, 2, 2), 16), ((7, 1, 1), 10), ((2, 5, 4), 5)])
+def test_x_face_pairs_summed_in_the_update_are_bit_identical(dims, N):
+    """The solvers' iterations sum the two-copy x-face groups inside the
+    update kernel instead of the exchange; nbx_pcg_iterate_noalloc runs the
+    same iterations with the full exchange plan.  The two sums are formed in
+    the same order, so every vector and scalar agrees bit for bit (one x
+    element: no pairs, the full plan on both sides)."""
+    print(f"x-pair update vs full exchange dims={dims} N={N}", flush=True)
+    b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
+    st = nbx.setup_brick(*dims, N, b.deform_array())
+    bh = host(st.b).reshape(-1)
+    dinv = st.problem.dinv()
+    c = 1.0 / host(st.gs.multiplicity())
+    z = host(dinv).reshape(-1) * bh
+    scal = np.zeros(nbx.SCAL_LEN)
+    scal[nbx.S_RHO] = float(np.sum(c * bh * z))
+    scal[nbx.S_STOP] = -1.0
+    scal[nbx.S_MAXIT] = 1e9
+    s0 = [np.zeros_like(bh), bh, z, np.zeros_like(bh), scal]
+    ref = [torch.as_tensor(a.copy()).cuda() for a in s0]
+    new = [torch.as_tensor(a.copy()).cuda() for a in s0]
+    w = torch.empty_like(ref[0])
+    st.problem.pcg_iterate(*ref, n_iter=9)
+    nbx.pcg_iterate_noalloc(nbx.pair_factors(st.G, N), st.D, N, st.gs, dinv, *new[:4], w,
+                            new[4], n_iter=9)
+    for name, a, c_ in zip(("x", "r", "z", "p", "scal"), ref, new):
+        assert np.array_equal(host(a), host(c_)), name
+    assert host(ref[4])[nbx.S_ITER] == 9

@@ -237,15 +237,18 @@ def test_shared_interior_node_keeps_jacobi_and_symmetry():
 
 
 def test_bf16_gradient_stays_within_the_bfloat16_bound_of_the_exact_one():
-    """The rounding-emulating gradient (the library's operand roundings)
-    differs from the exact chain rule by the bfloat16 round-off, not more:
-    a wrong factor or a dropped term in it would show as an O(1) gap."""
+    """The rounding-emulating gradient (the library's operand roundings) is
+    the exact chain rule when the rounding is switched off, and differs
+    from it by the bfloat16 round-off, not more, when it is on."""
     N = 5
     P = O.setup(S.Brick(2, 2, 2, N, ((0.05, 2, 2, 2),) * 3))
     shape = lpi.Shape(N, n_hid=32)
     prm = _random_params(shape, seed=13)
     X, T, F, _ = lpi.sample_rows(P, S.uniform_field(P.E, N, seed=3).reshape(-1))
     l0, g0 = lpi.loss_and_grad(shape, prm, X, T, F)
+    lx, gx = lpi.loss_and_grad_bf16(shape, prm, X, T, F, rnd=lambda a: a)
+    assert abs(lx - l0) <= 1e-14 * l0
+    np.testing.assert_allclose(gx, g0, rtol=1e-12, atol=1e-15)
     l1, g1 = lpi.loss_and_grad_bf16(shape, prm, X, T, F)
     assert abs(l1 - l0) <= 2 ** -6 * l0
     for a, b in zip(shape.unpack(g1), shape.unpack(g0)):

@@ -122,3 +122,18 @@ def test_fpcg_detects_breakdown():
     with pytest.raises(M.FpcgBreakdown) as ei:
         M.fpcg(P.apply_A, flip, P.b, P.c, max_iter=50)
     assert ei.value.iteration == 1
+
+
+def test_rounding_emulation_without_rounding_is_the_chain_rule():
+    """The rounding-emulating gradient with the rounding switched off is
+    the exact chain rule (every term and transpose in it is the same); with
+    bfloat16 rounding the forward pass stays within the bfloat16 bound."""
+    shape, params, X, T = _small()
+    l0, g0 = M.loss_and_grad(shape, params, X, T)
+    l1, g1, Y1 = M.loss_and_grad_bf16(shape, params, X, T, rnd=lambda a: a)
+    _, _, Y0 = M.forward(shape, params, X)
+    np.testing.assert_allclose(Y1, Y0, rtol=1e-14, atol=1e-14)
+    assert abs(l1 - l0) <= 1e-14 * l0
+    np.testing.assert_allclose(g1, g0, rtol=1e-12, atol=1e-15)
+    _, _, Yb = M.loss_and_grad_bf16(shape, params, X, T)
+    assert np.abs(Yb - Y0).max() <= 2 ** -5 * np.abs(Y0).max()
