@@ -14,9 +14,12 @@
 // the solve is flexible CG (Notay 2000, one stored direction:
 // beta = -<z', A p> / <p, A p>), which tolerates that.
 //
-// Application per CG iteration: gather r_S into BF16 rows [E][nIp], one
-// GEMM X L^T with the gains multiplied in its epilogue (BF16 out), one GEMM
-// with L (FP32 out), and the kernel that forms z, <r, z>_c and <z, A p>_c.
+// Application per CG iteration: r_S gathered into BF16 rows [E][nIp] by
+// the update step that produces r, one GEMM X L^T with the gains
+// multiplied in its epilogue (BF16 out), one GEMM with L (FP32 out), and
+// the kernel that forms z, <r, z>_c and <z, A p>_c.  The node-wise kernels
+// are instantiated per N, so the node-to-interior-index arithmetic needs no
+// run-time division.
 //
 // Training rows from a vector v the FP64 solver produced (an error x* - x,
 // formed here as the difference of two vectors, or a residual r):
@@ -162,31 +165,6 @@ __device__ __forceinline__ double lp_z(int N, int64_t N3, int64_t l, double rl, 
     return dl * rl;
 }
 
-// z_new from r and the learned rows; partials of <r, z_new>_c and
-// <z_new, w>_c (w = A p of the step just taken; not read on the first
-// application); z = z_new.
-__global__ void __launch_bounds__(sk::kRedThreads)
-lp_dots_kernel(int N, int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
-               const uint8_t *__restrict__ info, const float *__restrict__ Zi, int nIp,
-               const double *__restrict__ igd, const double *__restrict__ w, int first,
-               double *__restrict__ z, double *__restrict__ part, const double *__restrict__ scal)
-{
-    if (scal[NBX_S_FLAG] != 0.0) return;
-    const int64_t N3 = (int64_t)N * N * N;
-    double a = 0, b = 0;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t inf = info[l];
-        const double c = sk::cw(inf), rl = r[l];
-        const double zn = lp_z(N, N3, l, rl, dinv[l], inf, Zi, nIp, igd);
-        a += c * rl * zn;
-        if (!first) b += c * zn * w[l];
-        z[l] = zn;
-    }
-    sk::block_sum2(a, b);
-    if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = b; }
-}
-
 // beta = -<z_new, w> / <p, w> (0 on the first application);
 // rho = <r, z_new>; breakdown if it is not positive.
 __global__ void __launch_bounds__(1024)
@@ -211,25 +189,138 @@ lp_beta_kernel(int nb, const double *__restrict__ part, double *__restrict__ sca
     }
 }
 
-// x += alpha p; r -= alpha w; partials of c r r (and 1 in the second slot).
+// Interior index of node p of an element (N a compile-time constant, so
+// the divisions become multiplications), -1 off the interior.
+template <int N>
+__device__ __forceinline__ int lp_iq(int p)
+{
+    const int i = p % N, j = (p / N) % N, k = p / (N * N);
+    if (i == 0 || i == N - 1 || j == 0 || j == N - 1 || k == 0 || k == N - 1) return -1;
+    constexpr int m = N - 2;
+    return (i - 1) + m * ((j - 1) + m * (k - 1));
+}
+
+// The update step with the next application's gather fused in: x += alpha
+// p; r -= alpha w; partials of c r r; and X[e][q] = bf16(r) on learned
+// interior nodes, 0 on the other interior nodes (the padding of X stays as
+// set at binding).  Two values per lane, the iteration's one pass over r.
+template <int N>
+__device__ __forceinline__ void lp_upd_node(int64_t l, double pl, double wl, uint8_t inf,
+                                            double alpha, double &xl, double &rl, double &rr,
+                                            int nIp, uint16_t *__restrict__ X)
+{
+    constexpr int64_t N3 = (int64_t)N * N * N;
+    xl = __builtin_fma(alpha, pl, xl);
+    rl = __builtin_fma(-alpha, wl, rl);
+    rr += sk::cw(inf) * rl * rl;
+    const int64_t e = l / N3;
+    const int q = lp_iq<N>((int)(l - e * N3));
+    if (q >= 0) X[e * nIp + q] = lp_learned(inf) ? lp_f2bf((float)rl) : (uint16_t)0;
+}
+
+template <int N>
 __global__ void __launch_bounds__(sk::kRedThreads)
-lp_update_kernel(int64_t n, const double *__restrict__ p, const double *__restrict__ w,
-                 const uint8_t *__restrict__ info, double *__restrict__ x,
-                 double *__restrict__ r, double *__restrict__ part,
-                 const double *__restrict__ scal)
+lp_update_gather_kernel(int64_t n, int nIp, const double *__restrict__ p,
+                        const double *__restrict__ w, const uint8_t *__restrict__ info,
+                        double *__restrict__ x, double *__restrict__ r,
+                        uint16_t *__restrict__ X, double *__restrict__ part,
+                        const double *__restrict__ scal)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
+    using V = sk::Vec<double>;
     const double alpha = scal[NBX_S_ALPHA];
     double rr = 0, one = 0;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        x[l] = __builtin_fma(alpha, p[l], x[l]);
-        const double rl = __builtin_fma(-alpha, w[l], r[l]);
-        r[l] = rl;
-        rr += sk::cw(info[l]) * rl * rl;
+    const int64_t nv = n / 2;
+    const V::v *pv = reinterpret_cast<const V::v *>(p);
+    const V::v *wv = reinterpret_cast<const V::v *>(w);
+    V::v *xv = reinterpret_cast<V::v *>(x);
+    V::v *rv = reinterpret_cast<V::v *>(r);
+    const V::iv *iv = reinterpret_cast<const V::iv *>(info);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const V::v pq = __builtin_nontemporal_load(pv + q);
+        const V::v wq = __builtin_nontemporal_load(wv + q);
+        V::v xq = __builtin_nontemporal_load(xv + q);
+        V::v rq = __builtin_nontemporal_load(rv + q);
+        const V::iv inf = __builtin_nontemporal_load(iv + q);
+        double x0 = xq[0], x1 = xq[1], r0 = rq[0], r1 = rq[1];
+        lp_upd_node<N>(2 * q, pq[0], wq[0], (uint8_t)inf, alpha, x0, r0, rr, nIp, X);
+        lp_upd_node<N>(2 * q + 1, pq[1], wq[1], (uint8_t)(inf >> 8), alpha, x1, r1, rr, nIp, X);
+        xq[0] = x0; xq[1] = x1; rq[0] = r0; rq[1] = r1;
+        __builtin_nontemporal_store(xq, xv + q);
+        __builtin_nontemporal_store(rq, rv + q);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) {
+        const int64_t l = n - 1;
+        double xl = x[l], rl = r[l];
+        lp_upd_node<N>(l, p[l], w[l], info[l], alpha, xl, rl, rr, nIp, X);
+        x[l] = xl; r[l] = rl;
     }
     sk::block_sum2(rr, one);
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = one; }
+}
+
+// z_new from r and the learned rows (Jacobi off the learned nodes);
+// partials of <r, z_new>_c and <z_new, w>_c (w = A p of the step just
+// taken; not read on the first application); z = z_new.  Two values per
+// lane.
+template <int N>
+__device__ __forceinline__ double lp_zn(int64_t l, double rl, double dl, uint8_t inf,
+                                        const float *__restrict__ Zi, int nIp,
+                                        const double *__restrict__ igd)
+{
+    constexpr int64_t N3 = (int64_t)N * N * N;
+    const int64_t e = l / N3;
+    const int q = lp_iq<N>((int)(l - e * N3));
+    if (q >= 0 && lp_learned(inf)) return (double)Zi[e * nIp + q] * igd[e];
+    return dl * rl;
+}
+
+template <int N>
+__global__ void __launch_bounds__(sk::kRedThreads)
+lp_dots_n_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ dinv,
+                 const uint8_t *__restrict__ info, const float *__restrict__ Zi, int nIp,
+                 const double *__restrict__ igd, const double *__restrict__ w, int first,
+                 double *__restrict__ z, double *__restrict__ part,
+                 const double *__restrict__ scal)
+{
+    if (scal[NBX_S_FLAG] != 0.0) return;
+    using V = sk::Vec<double>;
+    double a = 0, b = 0;
+    const int64_t nv = n / 2;
+    const V::v *rv = reinterpret_cast<const V::v *>(r);
+    const V::v *dv = reinterpret_cast<const V::v *>(dinv);
+    const V::v *wv = reinterpret_cast<const V::v *>(w);
+    V::v *zv = reinterpret_cast<V::v *>(z);
+    const V::iv *iv = reinterpret_cast<const V::iv *>(info);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const V::v rq = __builtin_nontemporal_load(rv + q);
+        const V::v dq = __builtin_nontemporal_load(dv + q);
+        const V::iv inf = __builtin_nontemporal_load(iv + q);
+        V::v zq;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint8_t ic = (uint8_t)(inf >> (8 * c));
+            zq[c] = lp_zn<N>(2 * q + c, rq[c], dq[c], ic, Zi, nIp, igd);
+            a += sk::cw(ic) * rq[c] * zq[c];
+        }
+        if (!first) {
+            const V::v wq = __builtin_nontemporal_load(wv + q);
+            b += sk::cw((uint8_t)inf) * zq[0] * wq[0];
+            b += sk::cw((uint8_t)(inf >> 8)) * zq[1] * wq[1];
+        }
+        __builtin_nontemporal_store(zq, zv + q);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) {
+        const int64_t l = n - 1;
+        const double zn = lp_zn<N>(l, r[l], dinv[l], info[l], Zi, nIp, igd);
+        a += sk::cw(info[l]) * r[l] * zn;
+        if (!first) b += sk::cw(info[l]) * zn * w[l];
+        z[l] = zn;
+    }
+    sk::block_sum2(a, b);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = b; }
 }
 
 // ITER++, RR; FLAG = 1 when RR <= STOP, 3 at MAXIT.
@@ -396,14 +487,10 @@ int compute_gains(nbx_lp *L, hipStream_t s)
     return NBX_OK;
 }
 
-// Zi = ((X L^T) * gamma) L for X = gather(r); flag may be null
-int enqueue_rows(nbx_lp *L, const double *r, const double *flag, hipStream_t s)
+// The two GEMMs of an application: Zi = ((X L^T) * gamma) L.
+int enqueue_gemms(nbx_lp *L, hipStream_t s)
 {
-    nbx_problem *P = L->P;
     const int n = L->nIp;
-    hipLaunchKernelGGL(lp_gather_kernel, dim3(lp_grid(L->Epad * n)), dim3(256), 0, s, L->N,
-                       L->nI, n, P->E, L->Epad, r, P->gs->plan.info, L->X, flag);
-    NBX_LAUNCH_CHECK();
     const uint16_t *Lb = lpi_Lb(L->M);
     for (int64_t r0 = 0; r0 < L->Epad; r0 += kGemmRows) {
         const int rows = (int)std::min<int64_t>(kGemmRows, L->Epad - r0);
@@ -418,16 +505,69 @@ int enqueue_rows(nbx_lp *L, const double *r, const double *flag, hipStream_t s)
     return NBX_OK;
 }
 
-// z <- M(r) inside the flexible iteration, with the dots and beta.
-int enqueue_precond(nbx_lp *L, double *scal, int first, hipStream_t s)
+// Zi = ((X L^T) * gamma) L for X = gather(r); flag may be null
+int enqueue_rows(nbx_lp *L, const double *r, const double *flag, hipStream_t s)
 {
     nbx_problem *P = L->P;
-    int st = enqueue_rows(L, P->r, scal + NBX_S_FLAG, s);
+    const int n = L->nIp;
+    hipLaunchKernelGGL(lp_gather_kernel, dim3(lp_grid(L->Epad * n)), dim3(256), 0, s, L->N,
+                       L->nI, n, P->E, L->Epad, r, P->gs->plan.info, L->X, flag);
+    NBX_LAUNCH_CHECK();
+    return enqueue_gemms(L, s);
+}
+
+#define LP_FOR_EACH_N(C) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14) C(15) C(16)
+
+// The update step with the gather fused (lp_update_gather_kernel<N>).
+int launch_update_gather(nbx_lp *L, double *x, hipStream_t s)
+{
+    nbx_problem *P = L->P;
+    const int nb = sk::red_blocks(P->n);
+    switch (L->N) {
+#define LP_CASE(NN)                                                                             \
+    case NN:                                                                                    \
+        hipLaunchKernelGGL(lp_update_gather_kernel<NN>, dim3(nb), dim3(sk::kRedThreads), 0, s,  \
+                           P->n, L->nIp, P->p, P->w, P->gs->plan.info, x, P->r, L->X, P->part3, \
+                           P->scal);                                                            \
+        break;
+        LP_FOR_EACH_N(LP_CASE)
+#undef LP_CASE
+        default: return NBX_EUNSUPPORTED;
+    }
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+// z_new, <r, z_new>_c and <z_new, w>_c from the learned rows (lp_dots_n_kernel<N>).
+int launch_dots(nbx_lp *L, double *scal, int first, hipStream_t s)
+{
+    nbx_problem *P = L->P;
+    const int nb = sk::red_blocks(P->n);
+    switch (L->N) {
+#define LP_CASE(NN)                                                                              \
+    case NN:                                                                                     \
+        hipLaunchKernelGGL(lp_dots_n_kernel<NN>, dim3(nb), dim3(sk::kRedThreads), 0, s, P->n,    \
+                           P->r, P->dinv, P->gs->plan.info, L->Zi, L->nIp, L->igd, P->w, first, \
+                           P->z, L->part4, scal);                                                \
+        break;
+        LP_FOR_EACH_N(LP_CASE)
+#undef LP_CASE
+        default: return NBX_EUNSUPPORTED;
+    }
+    NBX_LAUNCH_CHECK();
+    return NBX_OK;
+}
+
+// z <- M(r) inside the flexible iteration, with the dots and beta.  With
+// gathered != 0, X already holds r's rows (the update step wrote them).
+int enqueue_precond(nbx_lp *L, double *scal, int first, int gathered, hipStream_t s)
+{
+    nbx_problem *P = L->P;
+    int st = gathered ? enqueue_gemms(L, s) : enqueue_rows(L, P->r, scal + NBX_S_FLAG, s);
+    if (st != NBX_OK) return st;
+    st = launch_dots(L, scal, first, s);
     if (st != NBX_OK) return st;
     const int nb = sk::red_blocks(P->n);
-    hipLaunchKernelGGL(lp_dots_kernel, dim3(nb), dim3(sk::kRedThreads), 0, s, L->N, P->n, P->r,
-                       P->dinv, P->gs->plan.info, L->Zi, L->nIp, L->igd, P->w, first, P->z,
-                       L->part4, scal);
     hipLaunchKernelGGL(lp_beta_kernel, dim3(1), dim3(1024), 0, s, nb, L->part4, scal, first);
     NBX_LAUNCH_CHECK();
     return NBX_OK;
@@ -446,11 +586,11 @@ int enqueue_flex_iters(nbx_lp *L, double *x, int n_iter, hipStream_t s)
                            P->scal);
         st = dssum_launch<double>(gs, P->w, 1, s, P->scal + NBX_S_FLAG);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(lp_update_kernel, dim3(nb3), dim3(sk::kRedThreads), 0, s, P->n, P->p,
-                           P->w, gs.info, x, P->r, P->part3, P->scal);
+        st = launch_update_gather(L, x, s);
+        if (st != NBX_OK) return st;
         hipLaunchKernelGGL(lp_rr_kernel, dim3(1), dim3(1024), 0, s, nb3, P->part3, P->scal);
         NBX_LAUNCH_CHECK();
-        st = enqueue_precond(L, P->scal, 0, s);
+        st = enqueue_precond(L, P->scal, 0, 1, s);
         if (st != NBX_OK) return st;
     }
     return NBX_OK;
@@ -504,6 +644,12 @@ extern "C" int nbx_lp_create(nbx_problem *P, nbx_lpi *M, nbx_lp **out, void *str
         return NBX_ENOMEM;
     }
     hipStream_t s = as_stream(stream);
+    // the padding of X (q >= nI, e >= E) stays zero: the fused update step
+    // writes only the interior rows
+    if (hipMemsetAsync(L->X, 0, rows * sizeof(uint16_t), s) != hipSuccess) {
+        nbx_lp_destroy(L);
+        return NBX_ENOMEM;
+    }
     const int N3 = N * N * N;
     hipLaunchKernelGGL(lp_geom_kernel, dim3((unsigned)P->E), dim3(256), 0, s, N3, P->G, L->gfeat,
                        L->igd);
@@ -608,7 +754,7 @@ extern "C" int nbx_pcg_learned(nbx_lp *L, const double *b, double *x, const nbx_
     hipLaunchKernelGGL(sk::init_reduce_kernel, dim3(1), dim3(1024), 0, s, nb, P->part3, P->scal,
                        o.rtol, o.fixed_iters, o.max_iter);
     NBX_LAUNCH_CHECK();
-    int st = enqueue_precond(L, P->scal, 1, s);
+    int st = enqueue_precond(L, P->scal, 1, 0, s);
     if (st != NBX_OK) return st;
     int done = 0;
     double *h = P->h_scal;
