@@ -79,11 +79,12 @@ void free_plan(GsPlan &p)
     p = GsPlan{};
 }
 
-int xpair_plan(const GsPlan &full, int64_t xd, GsPlan &out, int *found)
+int xpair_plan(const GsPlan &full, int N, GsPlan &out, int *found)
 {
     *found = 0;
     out = GsPlan{};
-    if (xd <= 0 || full.n_groups == 0) return NBX_OK;
+    if (N < 2 || full.n_groups == 0) return NBX_OK;
+    const int64_t xd = xpair_offset(N);
     std::vector<int32_t> off, idx, mask_idx;
     std::vector<uint8_t> gflag, info;
     int st = dev_download(full.off, (size_t)full.n_groups + 1, off);
@@ -99,7 +100,8 @@ int xpair_plan(const GsPlan &full, int64_t xd, GsPlan &out, int *found)
     int64_t pairs = 0;
     for (int32_t g = 0; g < full.n_groups; ++g) {
         const int32_t b = off[g], e = off[g + 1];
-        if (e - b == 2 && !gflag[g] && (int64_t)idx[b + 1] - idx[b] == xd) {
+        if (e - b == 2 && !gflag[g] && (int64_t)idx[b + 1] - idx[b] == xd &&
+            idx[b] % N == N - 1) {
             info[idx[b]] = (uint8_t)((info[idx[b]] & kXpMult) | kXpNext);
             info[idx[b + 1]] = (uint8_t)((info[idx[b + 1]] & kXpMult) | kXpPrev);
             ++pairs;

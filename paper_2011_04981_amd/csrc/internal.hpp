@@ -62,17 +62,19 @@ struct GsPlan {
 };
 
 // The exchange plan of the solvers' iterations, derived from a full plan:
-// two-copy non-Dirichlet groups whose local indices are a and a + xd (for
-// the lexicographic element order, xd = N^3 - N + 1 pairs the last x-face
-// of an element with the first of the next one) leave the plan, and the
-// update kernel sums them from w instead, reading the pair's second value
-// from a line that its neighbourhood streams anyway.  The derived plan's
-// info byte carries the multiplicity in bits 0..4 (kXpMult), kXpNext at a,
-// kXpPrev at a + xd, and the Dirichlet bit 7.  Synchronous (reads the full
-// plan back); *found = 0, and nothing allocated, when no such pair exists or
-// a multiplicity exceeds kXpMult.
+// two-copy non-Dirichlet groups whose local indices are a and a + xd with
+// xd = N^3 - N + 1 and a % N == N - 1 (the last x-face node of a row of an
+// element and the first of the same row in the next element, the
+// lexicographic element order's x neighbour) leave the plan, and the update
+// kernel sums them from w instead, reading the pair's second value from a
+// line that its neighbourhood streams anyway.  The derived plan's info byte
+// carries the multiplicity in bits 0..4 (kXpMult), kXpNext at a, kXpPrev at
+// a + xd, and the Dirichlet bit 7.  Synchronous (reads the full plan back);
+// *found = 0, and nothing allocated, when no such pair exists or a
+// multiplicity exceeds kXpMult.
 constexpr uint8_t kXpMult = 0x1f, kXpNext = 0x20, kXpPrev = 0x40;
-int xpair_plan(const GsPlan &full, int64_t xd, GsPlan &out, int *found);
+inline int64_t xpair_offset(int N) { return (int64_t)N * N * N - N + 1; }
+int xpair_plan(const GsPlan &full, int N, GsPlan &out, int *found);
 void free_plan(GsPlan &p);
 
 // Enqueue dssum on a double or float vector.  With `flag` (device), the

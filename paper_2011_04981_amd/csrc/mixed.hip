@@ -86,7 +86,7 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
         if (P->xd)
             hipLaunchKernelGGL(sk::update_xp_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0,
                                s, P->n, P->p32, P->w32, P->dinv32, gs.info, P->d32, P->r32,
-                               P->z32, P->part3, P->scal32, P->xd);
+                               P->z32, P->part3, P->scal32, P->xd, P->N);
         else
             hipLaunchKernelGGL(sk::update_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
                                P->n, P->p32, P->w32, P->dinv32, gs.info, P->d32, P->r32,

@@ -56,7 +56,8 @@ static int enqueue_iters_on(const IterArgs &a, double *x, double *r, double *z, 
         if (st != NBX_OK) return st;
         if (a.xd)
             hipLaunchKernelGGL(sk::update_xp_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0,
-                               s, a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal, a.xd);
+                               s, a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal, a.xd,
+                               a.N);
         else
             hipLaunchKernelGGL(sk::update_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0, s,
                                a.n, p, a.w, a.dinv, gs.info, x, r, z, a.part3, scal);
@@ -198,11 +199,10 @@ extern "C" int nbx_problem_create(const double *G, const double *D, int N, int64
     if (st != NBX_OK) return fail(st);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize"));
-    const int64_t xd = (int64_t)N * N * N - N + 1;
     int found = 0;
-    st = xpair_plan(gs->plan, xd, P->xplan, &found);
+    st = xpair_plan(gs->plan, N, P->xplan, &found);
     if (st != NBX_OK) return fail(st);
-    if (found) P->xd = xd;
+    if (found) P->xd = xpair_offset(N);
     *out = P;
     return NBX_OK;
 }

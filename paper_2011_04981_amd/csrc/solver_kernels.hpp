@@ -198,15 +198,28 @@ template <> struct Vec<float> {
 
 // The exchange of an x-face pair done inside K3: the assembled value of a
 // pair (a, a + xd) is the exchange's own sum, (0 + w[a]) + w[a + xd] with
-// the lower local index first, so the result has the same bits.
+// the lower local index first, so the result has the same bits.  wo is the
+// partner's value (read by position, see update_body).
 template <typename T>
-__device__ __forceinline__ T xpair_w(T wl, uint8_t inf, const T *__restrict__ w, int64_t l,
-                                     int64_t xd)
+__device__ __forceinline__ T xpair_w(T wl, T wo, uint8_t inf)
 {
     T s = 0;
-    if (inf & kXpNext) { s += wl; s += w[l + xd]; return s; }
-    if (inf & kXpPrev) { s += w[l - xd]; s += wl; return s; }
+    if (inf & kXpNext) { s += wl; s += wo; return s; }
+    if (inf & kXpPrev) { s += wo; s += wl; return s; }
     return wl;
+}
+
+// The partner value a node may need: x-pair nodes sit at the ends of the
+// element rows (i = N - 1 pairs with l + xd, i = 0 with l - xd), so the
+// load depends on the position only and is issued with the stream's own
+// loads instead of after the info byte has arrived.
+template <typename T>
+__device__ __forceinline__ T xpair_partner(const T *__restrict__ w, int64_t l, uint32_t i,
+                                           int xn, int64_t xd, int64_t n)
+{
+    if (i == (uint32_t)xn - 1 && l + xd < n) return w[l + xd];
+    if (i == 0 && l >= xd) return w[l - xd];
+    return 0;
 }
 
 // K3: x += alpha p; r -= alpha w; z = dinv r; partials of c r r and c r z.
@@ -217,7 +230,8 @@ __device__ __forceinline__ void
 update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
             const T *__restrict__ dinv, const uint8_t *__restrict__ info, T *__restrict__ x,
             T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
-            const double *__restrict__ scal, int64_t blk, int64_t nblk, int64_t xd = 0)
+            const double *__restrict__ scal, int64_t blk, int64_t nblk, int64_t xd = 0,
+            int xn = 0)
 {
     if (scal[NBX_S_FLAG] != 0.0) return;
     using V = Vec<T>;
@@ -242,11 +256,21 @@ update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
         typename V::v rq = __builtin_nontemporal_load(rv + q);
         typename V::v zq;
         const typename V::iv inf = __builtin_nontemporal_load(iv + q);
+        [[maybe_unused]] T wo[W];
+        if constexpr (XP) {
+            // n < 2^31 (the exchange plan's limit): 32-bit position arithmetic
+            uint32_t i = (uint32_t)(q * W) % (uint32_t)xn;
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                wo[c] = xpair_partner<T>(w, q * W + c, i, xn, xd, n);
+                i = i + 1 == (uint32_t)xn ? 0 : i + 1;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             const uint8_t ic = (uint8_t)(inf >> (8 * c));
             T wc = wq[c];
-            if constexpr (XP) wc = xpair_w<T>(wc, ic, w, q * W + c, xd);
+            if constexpr (XP) wc = xpair_w<T>(wc, wo[c], ic);
             xq[c] = fmaT(alpha, pq[c], xq[c]);
             rq[c] = fmaT(-alpha, wc, rq[c]);
             zq[c] = dq[c] * rq[c];
@@ -262,7 +286,9 @@ update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
         for (int64_t l = nv * W; l < n; ++l) {
             x[l] = fmaT(alpha, p[l], x[l]);
             T wl = w[l];
-            if constexpr (XP) wl = xpair_w<T>(wl, info[l], w, l, xd);
+            if constexpr (XP)
+                wl = xpair_w<T>(wl, xpair_partner<T>(w, l, (uint32_t)(l % xn), xn, xd, n),
+                                info[l]);
             const T rl = fmaT(-alpha, wl, r[l]), zl = dinv[l] * rl;
             const double cc = XP ? cw_x(info[l]) : cw(info[l]);
             r[l] = rl; z[l] = zl;
@@ -274,6 +300,17 @@ update_body(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
     if (threadIdx.x == 0) { part[2 * blk] = rr; part[2 * blk + 1] = rz; }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin; renumbered so that each
+// XCD takes one contiguous range of chunks, the neighbouring chunks (and
+// an x-face pair's two values, N^3 - N + 1 apart) share its L2.  A
+// bijection of [0, nblk) that keeps block 0 first, so the partial sums
+// land in the same slots as without it.
+__device__ __forceinline__ int64_t xcd_block(int64_t blk, int64_t nblk)
+{
+    const int64_t per = nblk / 8, rem = nblk % 8, x = blk % 8;
+    return x * per + (x < rem ? x : rem) + blk / 8;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
@@ -281,7 +318,8 @@ update_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
               T *__restrict__ r, T *__restrict__ z, double *__restrict__ part,
               const double *__restrict__ scal)
 {
-    update_body<T>(n, p, w, dinv, info, x, r, z, part, scal, blockIdx.x, gridDim.x);
+    update_body<T>(n, p, w, dinv, info, x, r, z, part, scal, xcd_block(blockIdx.x, gridDim.x),
+                   gridDim.x);
 }
 
 template <typename T>
@@ -289,9 +327,11 @@ __global__ void __launch_bounds__(kRedThreads)
 update_xp_kernel(int64_t n, const T *__restrict__ p, const T *__restrict__ w,
                  const T *__restrict__ dinv, const uint8_t *__restrict__ info,
                  T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
-                 double *__restrict__ part, const double *__restrict__ scal, int64_t xd)
+                 double *__restrict__ part, const double *__restrict__ scal, int64_t xd,
+                 int xn)
 {
-    update_body<T, true>(n, p, w, dinv, info, x, r, z, part, scal, blockIdx.x, gridDim.x, xd);
+    update_body<T, true>(n, p, w, dinv, info, x, r, z, part, scal,
+                         xcd_block(blockIdx.x, gridDim.x), gridDim.x, xd, xn);
 }
 
 // R3: rr, rho'; convergence / breakdown / iteration limit; beta.  With
