@@ -336,6 +336,10 @@ def main():
                      "median_launch_us": round(statistics.median(per) * 1e6, 2),
                      "min_launch_us": round(min(per) * 1e6, 2),
                      "max_launch_us": round(max(per) * 1e6, 2),
+                     # each timed launch in launch order (HIP events on the
+                     # launch stream), to show where slow launches sit
+                     "launch_us_in_order": ([round(x * 1e6, 1) for x in per]
+                                            if len(per) <= 100 else None),
                      "prewarm_ms": round(prewarm_ms, 1),
                      "prewarm_launches": pw_launches,
                      "paired_layout": {

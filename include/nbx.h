@@ -264,6 +264,18 @@ int nbx_problem_create(const double *G, const double *D, int N, int64_t E, nbx_g
 int nbx_problem_destroy(nbx_problem *p);
 /* Copies the problem's dinv into out[n_local] (device).  Async. */
 int nbx_problem_dinv(nbx_problem *p, double *out, void *stream);
+/* The exchange of the solvers' iterations (Section II-B's nearest-neighbour
+ * exchange): at nbx_problem_create the two-copy, non-Dirichlet groups of
+ * x faces (node a with a % N == N-1, the last node of an element row, and
+ * node a + d, d = N^3 - N + 1, the first node of the same row in the next
+ * element) leave the gather-scatter plan, and the solvers' update step
+ * sums them in the exchange's own order, so results are bit-identical to
+ * the full exchange.  out[0] = groups of the full plan, out[1] = groups the
+ * solvers' exchange keeps, out[2] = d (0 when no pair was taken and the
+ * solvers use the full plan), out[3] = out[4] = 0 (y and z face pairs stay
+ * in the exchange).  Host memory; synchronous, no GPU work.  NBX_EINVAL for
+ * null arguments. */
+int nbx_problem_exchange_info(nbx_problem *p, int64_t out[5]);
 
 /* Length of the device scalar block used by nbx_pcg_iterate. */
 #define NBX_SCAL_LEN 16

@@ -89,6 +89,7 @@ def lib():
         "nbx_problem_create": ([vp, vp, i32, i64, vp, C.POINTER(vp), vp], i32),
         "nbx_problem_destroy": ([vp], i32),
         "nbx_problem_dinv": ([vp, vp, vp], i32),
+        "nbx_problem_exchange_info": ([vp, vp], i32),
         "nbx_repack_g_aos_to_soa": ([vp, vp, i32, i64, vp], i32),
         "nbx_pair_factors": ([vp, vp, i32, i64, vp], i32),
         "nbx_pcg_iterate": ([vp, vp, vp, vp, vp, vp, i32, vp], i32),
@@ -550,6 +551,15 @@ class Problem:
         out = torch.empty((self.E, self.N ** 3), dtype=torch.float64, device=self.device)
         _check(lib().nbx_problem_dinv(self._h, _dptr(out), _stream(stream)), "nbx_problem_dinv")
         return out
+
+    def exchange_info(self) -> dict:
+        """Groups of the full exchange plan and of the solvers' exchange, and
+        the offsets of the face pairs the update step sums (x, y, z; only x
+        pairs are taken)."""
+        out = (C.c_int64 * 5)()
+        _check(lib().nbx_problem_exchange_info(self._h, out), "nbx_problem_exchange_info")
+        return {"full_groups": out[0], "solver_groups": out[1],
+                "pair_offsets": (out[2], out[3], out[4])}
 
     def pcg(self, b, x=None, stream=None, **opts) -> tuple:
         torch = _torch()

@@ -234,6 +234,16 @@ extern "C" int nbx_problem_dinv(nbx_problem *P, double *out, void *stream)
     return NBX_OK;
 }
 
+extern "C" int nbx_problem_exchange_info(nbx_problem *P, int64_t out[5])
+{
+    if (!P || !out) return NBX_EINVAL;
+    out[0] = P->gs->plan.n_groups;
+    out[1] = iter_plan(P).n_groups;
+    out[2] = P->xd;   // x-face pairs only
+    out[3] = out[4] = 0;
+    return NBX_OK;
+}
+
 extern "C" int nbx_pcg_iterate(nbx_problem *P, double *x, double *r, double *z, double *pdir,
                                double *scal, int n_iter, void *stream)
 {

@@ -629,16 +629,25 @@ def test_mixed_solve_with_interior_shared_node(prec):
 
 
 @pytest.mark.parametrize("dims,N", [((1, 3, 2), 4), ((5, 2, 3), 2), ((4, 3, 3), 7),
-                                    ((3, 2, 2), 16), ((7, 1, 1), 10), ((2, 5, 4), 5)])
+                                    ((3, 2, 2), 16), ((7, 1, 1), 10), ((2, 5, 4), 5),
+                                    ((1, 1, 1), 6)])
 def test_x_face_pairs_summed_in_the_update_are_bit_identical(dims, N):
     """The solvers' iterations sum the two-copy x-face groups inside the
     update kernel instead of the exchange; nbx_pcg_iterate_noalloc runs the
     same iterations with the full exchange plan.  The two sums are formed in
-    the same order, so every vector and scalar agrees bit for bit (one x
-    element: no pairs, the full plan on both sides)."""
+    the same order, so every vector and scalar agrees bit for bit.  The pair
+    offset is the brick's x element stride N^3 - N + 1 (no pairs with one
+    element in x, and none at N = 2, where every face node is an element
+    corner with four or more copies or lies on the Dirichlet boundary)."""
     print(f"x-pair update vs full exchange dims={dims} N={N}", flush=True)
+    ex, ey, ez = dims
     b = S.Brick(*dims, N, ((0.05, 2, 2, 2),) * 3)
     st = nbx.setup_brick(*dims, N, b.deform_array())
+    info = st.problem.exchange_info()
+    want = (N ** 3 - N + 1 if ex > 1 and N > 2 else 0, 0, 0)
+    print(f"  {info}", flush=True)
+    assert info["pair_offsets"] == want
+    assert (info["solver_groups"] < info["full_groups"]) == (want[0] != 0)
     bh = host(st.b).reshape(-1)
     dinv = st.problem.dinv()
     c = 1.0 / host(st.gs.multiplicity())
