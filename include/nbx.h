@@ -218,11 +218,14 @@ int nbx_ax_mfma(int gprec, const float *u, const void *G, const float *gscale, c
 typedef struct nbx_gs nbx_gs;
 
 /* Builds the gather-scatter plan from host global ids (gid_host[n_local],
- * equal ids = same global node) and Dirichlet flags (bnd_host, may be NULL
- * for none).  Allocates device arrays; synchronous.  NBX_EUNSUPPORTED if
+ * equal ids = same global node) and Dirichlet flags (dirichlet_host[n_local],
+ * nonzero = on the Dirichlet boundary; may be NULL for none).  Allocates
+ * device arrays and uploads them on `stream`; returns once the plan is on
+ * the device (synchronous).  NBX_EINVAL for a null gid_host with
+ * n_local > 0, n_local < 0 or a null out; NBX_EUNSUPPORTED if
  * n_local >= 2^31 or a node has more than 127 copies. */
-int nbx_gs_create(const int64_t *gid_host, const uint8_t *bnd_host, int64_t n_local,
-                  nbx_gs **out);
+int nbx_gs_create(const int64_t *gid_host, int64_t n_local, const uint8_t *dirichlet_host,
+                  nbx_gs **out, void *stream);
 int nbx_gs_destroy(nbx_gs *gs);
 
 /* In place: v_l <- sum of v over l's global node, summed in ascending local

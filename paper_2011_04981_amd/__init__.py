@@ -79,7 +79,7 @@ def lib():
         "nbx_ax_get_tile": ([i32, i32], i32),
         "nbx_pcg_set_tile": ([i32, i32, i32], i32),
         "nbx_pcg_get_tile": ([i32, i32], i32),
-        "nbx_gs_create": ([vp, vp, i64, C.POINTER(vp)], i32),
+        "nbx_gs_create": ([vp, i64, vp, C.POINTER(vp), vp], i32),
         "nbx_gs_destroy": ([vp], i32),
         "nbx_dssum": ([vp, i32, vp, i32, vp], i32),
         "nbx_gs_multiplicity": ([vp, vp, vp], i32),
@@ -421,8 +421,8 @@ class GS:
         if b is not None and b.size != self.n:
             raise ValueError("one Dirichlet flag per local node")
         h = C.c_void_p()
-        _check(lib().nbx_gs_create(_hptr(gid), _hptr(b) if b is not None else None,
-                                   self.n, C.byref(h)), "nbx_gs_create")
+        _check(lib().nbx_gs_create(_hptr(gid), self.n, _hptr(b) if b is not None else None,
+                                   C.byref(h), _stream(None)), "nbx_gs_create")
         self._h = h
 
     @property

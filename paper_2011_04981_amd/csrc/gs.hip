@@ -48,16 +48,18 @@ __global__ void multiplicity_kernel(int64_t n, const uint8_t *__restrict__ info,
     if (l < n) out[l] = (double)(info[l] & 0x7f);
 }
 
+// Device copy of h (the copy is issued on s; the caller synchronises s
+// before h goes out of scope).
 template <typename T>
-void *dev_upload(const std::vector<T> &h, int &st)
+void *dev_upload(const std::vector<T> &h, int &st, hipStream_t s = nullptr)
 {
     void *p = nullptr;
     const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) { st = NBX_ENOMEM; return nullptr; }
     if (!h.empty()) {
-        e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
-        if (e != hipSuccess) { st = hip_fail(e, "hipMemcpy"); hipFree(p); return nullptr; }
+        e = hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { st = hip_fail(e, "hipMemcpyAsync"); hipFree(p); return nullptr; }
     }
     return p;
 }
@@ -120,6 +122,8 @@ int xpair_plan(const GsPlan &full, int N, GsPlan &out, int *found)
     if (st == NBX_OK) out.gflag = (uint8_t *)dev_upload(rflag, st);
     if (st == NBX_OK) out.mask_idx = (int32_t *)dev_upload(mask_idx, st);
     if (st == NBX_OK) out.info = (uint8_t *)dev_upload(info, st);
+    const hipError_t e = hipStreamSynchronize(nullptr);   // the host vectors die here
+    if (st == NBX_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     if (st != NBX_OK) { free_plan(out); return st; }
     *found = 1;
     return NBX_OK;
@@ -146,8 +150,8 @@ template int dssum_launch<float>(const GsPlan &, float *, int, hipStream_t, cons
 
 using namespace nbx;
 
-extern "C" int nbx_gs_create(const int64_t *gid_host, const uint8_t *bnd_host, int64_t n_local,
-                             nbx_gs **out)
+extern "C" int nbx_gs_create(const int64_t *gid_host, int64_t n_local,
+                             const uint8_t *bnd_host, nbx_gs **out, void *stream)
 {
     if (!out || n_local < 0 || (n_local > 0 && !gid_host)) return NBX_EINVAL;
     *out = nullptr;
@@ -186,11 +190,14 @@ extern "C" int nbx_gs_create(const int64_t *gid_host, const uint8_t *bnd_host, i
     p.n_groups = (int32_t)gflag.size();
     p.n_mask_only = (int32_t)mask_idx.size();
     int st = NBX_OK;
-    p.off = (int32_t *)dev_upload(off, st);
-    if (st == NBX_OK) p.idx = (int32_t *)dev_upload(idx, st);
-    if (st == NBX_OK) p.gflag = (uint8_t *)dev_upload(gflag, st);
-    if (st == NBX_OK) p.mask_idx = (int32_t *)dev_upload(mask_idx, st);
-    if (st == NBX_OK) p.info = (uint8_t *)dev_upload(info, st);
+    hipStream_t s = as_stream(stream);
+    p.off = (int32_t *)dev_upload(off, st, s);
+    if (st == NBX_OK) p.idx = (int32_t *)dev_upload(idx, st, s);
+    if (st == NBX_OK) p.gflag = (uint8_t *)dev_upload(gflag, st, s);
+    if (st == NBX_OK) p.mask_idx = (int32_t *)dev_upload(mask_idx, st, s);
+    if (st == NBX_OK) p.info = (uint8_t *)dev_upload(info, st, s);
+    const hipError_t e = hipStreamSynchronize(s);   // the host vectors die here
+    if (st == NBX_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     if (st != NBX_OK) { free_plan(p); delete gs; return st; }
     *out = gs;
     return NBX_OK;

@@ -85,6 +85,6 @@ def test_ax_argument_validation_without_gpu():
 def test_gs_create_rejects_bad_arguments_without_gpu():
     L = nbx.lib()
     h = C.c_void_p()
-    assert L.nbx_gs_create(None, None, -1, C.byref(h)) == -1
-    assert L.nbx_gs_create(None, None, 5, C.byref(h)) == -1
-    assert L.nbx_gs_create(None, None, 5, None) == -1
+    assert L.nbx_gs_create(None, -1, None, C.byref(h), None) == -1
+    assert L.nbx_gs_create(None, 5, None, C.byref(h), None) == -1
+    assert L.nbx_gs_create(None, 5, None, None, None) == -1
