@@ -110,8 +110,10 @@ def _brick(dims, N, amp=0.06, rhs="sine"):
                    rhs, 7)
 
 
-@pytest.mark.parametrize("N,dims", [(5, (3, 2, 2)), (8, (2, 2, 2)), (10, (4, 3, 2))])
+@pytest.mark.parametrize("N,dims", [(5, (3, 2, 2)), (8, (2, 2, 2)), (10, (4, 3, 2)),
+                                    (8, (32, 16, 16))])
 def test_apply_matches_reference(N, dims):
+    # 32x16x16 at N = 8: a training brick's 8192 elements in one application
     print(f"learned apply N={N} dims={dims}", flush=True)
     b = _brick(dims, N)
     P = O.setup(b)
