@@ -319,7 +319,8 @@ int nbx_pcg_iterate(nbx_problem *p, double *x, double *r, double *z, double *pdi
  * everything the iterations read and write: the factors as factor pairs
  * Gp[E][3][N^3][2] (nbx_pair_factors), D, a plan gs for E N^3 local nodes,
  * dinv (e.g. from nbx_jacobi_setup), the state x, r, z, pdir and scal as
- * for nbx_pcg_iterate, and w[E][N^3], which receives A p of the last step.
+ * for nbx_pcg_iterate, and w[E][N^3], which receives A p of the last step
+ * (unspecified after a step that breaks down).
  * The reduction partials live in a fixed device array per GPU (looked up on
  * the first call on each device): every call on one GPU shares it, so calls
  * that overlap on one GPU race; nothing needs clearing between calls.

@@ -9,6 +9,7 @@
 // no atomics, deterministic, and bit-identical to a sequential sum in
 // ascending local order.
 #include "gs_kernels.hpp"
+#include "solver_kernels.hpp"
 
 #include <algorithm>
 #include <numeric>
@@ -20,18 +21,29 @@ namespace {
 // Threads [0, n_groups) sum one shared group each; with apply_mask the
 // threads after them zero the unshared Dirichlet nodes (one launch for
 // both steps).
+// With pap_part, the last workgroup performs the alpha step (PapTask) and
+// the others the exchange.
 template <typename T>
 __global__ void __launch_bounds__(kGsThreads)
 dssum_kernel(int32_t n_groups, const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
              const uint8_t *__restrict__ gflag, T *__restrict__ v, int apply_mask,
              int32_t n_mask, const int32_t *__restrict__ mask_idx,
-             const double *__restrict__ flag)
+             const double *__restrict__ flag, int pap_nb, const double *__restrict__ pap_part,
+             double *__restrict__ pap_scal)
 {
+    unsigned nblk = gridDim.x;
+    if (pap_part) {
+        if (blockIdx.x == gridDim.x - 1) {
+            sk::pap_reduce_body(pap_nb, pap_part, pap_scal);
+            return;
+        }
+        --nblk;
+    }
     if (flag && *flag != 0.0) return;   // uniform: solve already finished
     // XCD-aware mapping: workgroups are dealt to the 8 XCDs round-robin, so
     // give each XCD a contiguous range of groups (neighbouring groups share
     // cache lines; each XCD has its own L2)
-    const int32_t per = (int32_t)(gridDim.x / 8);
+    const int32_t per = (int32_t)(nblk / 8);
     const int32_t vb = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
     const int32_t g = vb * blockDim.x + threadIdx.x;
     if (g < n_groups) {
@@ -130,21 +142,25 @@ int xpair_plan(const GsPlan &full, int N, GsPlan &out, int *found)
 }
 
 template <typename T>
-int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const double *flag)
+int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s, const double *flag,
+                 const PapTask *pap)
 {
     const int64_t nt = (int64_t)gs.n_groups + (apply_mask ? gs.n_mask_only : 0);
-    if (nt > 0) {
+    if (nt > 0 || pap) {
         const int64_t nb = ((nt + kGsThreads - 1) / kGsThreads + 7) / 8 * 8;   // 8 XCDs
-        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)nb), dim3(kGsThreads), 0, s,
-                           gs.n_groups, gs.off, gs.idx, gs.gflag, v, apply_mask,
-                           gs.n_mask_only, gs.mask_idx, flag);
+        hipLaunchKernelGGL(dssum_kernel<T>, dim3((unsigned)(nb + (pap ? 1 : 0))),
+                           dim3(kGsThreads), 0, s, gs.n_groups, gs.off, gs.idx, gs.gflag, v,
+                           apply_mask, gs.n_mask_only, gs.mask_idx, flag, pap ? pap->nb : 0,
+                           pap ? pap->part : nullptr, pap ? pap->scal : nullptr);
         NBX_LAUNCH_CHECK();
     }
     return NBX_OK;
 }
 
-template int dssum_launch<double>(const GsPlan &, double *, int, hipStream_t, const double *);
-template int dssum_launch<float>(const GsPlan &, float *, int, hipStream_t, const double *);
+template int dssum_launch<double>(const GsPlan &, double *, int, hipStream_t, const double *,
+                                  const PapTask *);
+template int dssum_launch<float>(const GsPlan &, float *, int, hipStream_t, const double *,
+                                 const PapTask *);
 
 }  // namespace nbx
 

@@ -77,11 +77,24 @@ inline int64_t xpair_offset(int N) { return (int64_t)N * N * N - N + 1; }
 int xpair_plan(const GsPlan &full, int N, GsPlan &out, int *found);
 void free_plan(GsPlan &p);
 
+// The step that forms alpha = rho / <p, A p> from the fused stage's nb
+// per-workgroup partials (the solvers' one-block reduction R1), run by one
+// more workgroup of the exchange launch: the partials are complete when
+// the exchange starts, nothing in the exchange reads alpha, and the
+// iteration saves a launch.
+struct PapTask {
+    int nb = 0;
+    const double *part = nullptr;
+    double *scal = nullptr;
+};
+
 // Enqueue dssum on a double or float vector.  With `flag` (device), the
-// kernels do nothing once *flag != 0 (a finished solve).
+// kernels do nothing once *flag != 0 (a finished solve).  With pap, the
+// launch also performs that reduction (bit for bit the solvers' one-block
+// kernel: same block size, same code).
 template <typename T>
 int dssum_launch(const GsPlan &gs, T *v, int apply_mask, hipStream_t s,
-                 const double *flag = nullptr);
+                 const double *flag = nullptr, const PapTask *pap = nullptr);
 
 // AX launch (double / float) on factor pairs, the solvers' layout.
 int ax_launch_f64(const double *u, const double *G, const double *D, int N, int64_t E,

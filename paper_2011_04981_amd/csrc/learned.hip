@@ -582,9 +582,8 @@ int enqueue_flex_iters(nbx_lp *L, double *x, int n_iter, hipStream_t s)
     for (int it = 0; it < n_iter; ++it) {
         int st = ax_pcg_launch_f64(P->G, P->D, P->N, P->E, P->z, P->p, P->w, P->part1, P->scal, s);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, P->part1,
-                           P->scal);
-        st = dssum_launch<double>(gs, P->w, 1, s, P->scal + NBX_S_FLAG);
+        const PapTask pap{nb1, P->part1, P->scal};   // R1 rides on the exchange launch
+        st = dssum_launch<double>(gs, P->w, 1, s, P->scal + NBX_S_FLAG, &pap);
         if (st != NBX_OK) return st;
         st = launch_update_gather(L, x, s);
         if (st != NBX_OK) return st;

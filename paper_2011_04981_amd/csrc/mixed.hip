@@ -79,9 +79,8 @@ int enqueue_iters32(nbx_problem *P, int n_iter, hipStream_t s)
                      : ax_pcg_launch_g16(P->inner_fmt, P->G16, P->gscale, P->D, P->N, P->E,
                                          P->z32, P->p32, P->w32, P->part1, P->scal32, s);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, P->part1,
-                           P->scal32);
-        st = dssum_launch<float>(gs, P->w32, 1, s, P->scal32 + NBX_S_FLAG);
+        const PapTask pap{nb1, P->part1, P->scal32};   // R1 rides on the exchange launch
+        st = dssum_launch<float>(gs, P->w32, 1, s, P->scal32 + NBX_S_FLAG, &pap);
         if (st != NBX_OK) return st;
         if (P->xd)
             hipLaunchKernelGGL(sk::update_xp_kernel<float>, dim3(nb3), dim3(sk::kRedThreads), 0,

@@ -3,10 +3,11 @@
 // nearest-neighbour exchange and global reductions, with a simple
 // preconditioner, read here as Jacobi).
 //
-// One iteration is five kernels, all scalars staying on the device:
+// One iteration is four kernels, all scalars staying on the device:
 //   K1  p = z + beta p, w = AX(p), per-block partials of p.w   (ax_kernel.hpp)
-//   R1  pap = sum of partials (fixed order), alpha = rho / pap
 //   K2  w = mask(dssum(w))                                      (gs.hip)
+//       + R1 in one more workgroup of the same launch: pap = sum of the
+//       partials (fixed order), alpha = rho / pap
 //   K3  x += alpha p, r -= alpha w, z = dinv r, partials of c r r and c r z
 //   R3  rr, rho' (fixed order), convergence / breakdown flag, beta
 // <p,w>_c is taken before the exchange: p is continuous and zero on the
@@ -50,9 +51,8 @@ static int enqueue_iters_on(const IterArgs &a, double *x, double *r, double *z, 
     for (int it = 0; it < n_iter; ++it) {
         int st = ax_pcg_launch_f64(a.Gp, a.D, a.N, a.E, z, p, a.w, a.part1, scal, s);
         if (st != NBX_OK) return st;
-        hipLaunchKernelGGL(sk::pap_reduce_kernel, dim3(1), dim3(1024), 0, s, nb1, a.part1,
-                           scal);
-        st = dssum_launch<double>(gs, a.w, 1, s, scal + NBX_S_FLAG);
+        const PapTask pap{nb1, a.part1, scal};   // R1 rides on the exchange launch
+        st = dssum_launch<double>(gs, a.w, 1, s, scal + NBX_S_FLAG, &pap);
         if (st != NBX_OK) return st;
         if (a.xd)
             hipLaunchKernelGGL(sk::update_xp_kernel<double>, dim3(nb3), dim3(sk::kRedThreads), 0,

@@ -384,7 +384,7 @@ def test_mixed_precision_solve(case, mode):
 
 def test_mixed_precision_falls_back_when_refinement_stalls():
     """An inner tolerance of 0.5 cannot give the tenfold reduction per outer
-    step the driver demands, so it must finish with FP64 PCG."""
+    step the refinement loop demands, so it must finish with FP64 PCG."""
     b = S.scaled_c2_brick(3, 6)
     st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
     x, res = st.problem.pcg(st.b, rtol=1e-10, max_iter=5000, prec=nbx.F32, inner_rtol=0.5,
