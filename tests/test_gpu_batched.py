@@ -41,6 +41,20 @@ def _problems():
     return out
 
 
+def test_batched_bit_identical_to_standalone_at_n16():
+    """The largest order, one element per workgroup in both the standalone
+    fused stage and the batched one: the solves agree bit for bit."""
+    b = S.Brick(3, 2, 2, 16, ((0.05, 2, 1, 1), (0.04, 1, 2, 1), (0.03, 1, 1, 2)), "random", 3)
+    f = torch.as_tensor(S.rhs_values(b)).cuda()
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, 16, b.deform_array(), f=f)
+    x, r = st.problem.pcg(st.b, rtol=1e-10, max_iter=3000, check_every=10)
+    xs, res, _ = nbx.pcg_batched([st.problem], [st.b], rtol=1e-10, max_iter=3000,
+                                 check_every=10)
+    print(f"N = 16: standalone {r.iters} it, batched {res[0].iters} it")
+    assert r.status == 0 and res[0].status == 0 and res[0].iters == r.iters
+    assert np.array_equal(host(xs[0]), host(x))
+
+
 def test_batched_bit_identical_to_standalone():
     probs = _problems()
     refs = []
