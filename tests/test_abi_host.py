@@ -88,3 +88,16 @@ def test_gs_create_rejects_bad_arguments_without_gpu():
     assert L.nbx_gs_create(None, -1, None, C.byref(h), None) == -1
     assert L.nbx_gs_create(None, 5, None, C.byref(h), None) == -1
     assert L.nbx_gs_create(None, 5, None, None, None) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus above 1 exits with status 2 and
+    a JSON line that says so, before anything touches a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
