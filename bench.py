@@ -480,10 +480,11 @@ def main():
     # ---- the same mesh at N = 8 and 12: FP64 PCG against the refinement
     # variants (N = 10 is the block above); and the paper's own element
     # size, N = 16, for the plain operator at E = 800 and E = 8000
-    if not a.no_sweep and not a.no_pcg and a.N == 10:
+    # (--no-pcg keeps the operator replay and skips the solves)
+    if not a.no_sweep and a.N == 10:
         sweep = {}
         with torch.cuda.stream(stream):
-            for Ns in (8, 12):
+            for Ns in ((8, 12) if not a.no_pcg else ()):
                 log(f"sweep: N={Ns}")
                 st = nbx.setup_brick(brick.ex, brick.ey, brick.ez, Ns, brick.deform_array())
                 stream.synchronize()
@@ -521,21 +522,32 @@ def main():
                 Gr = torch.as_tensor(S.random_factors(Er, Nr, seed=1)).to(dev)
                 Dr = nbx.deriv_device(Nr, dev)
                 wr = torch.empty_like(ur)
-                for _ in range(20):
-                    nbx.ax(ur, Gr, Dr, out=wr)
-                e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(100):
-                    nbx.ax(ur, Gr, Dr, out=wr)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                t = e0.elapsed_time(e1) * 1e-3 / 100
+                # nbx_ax (FP64 N = 16 runs on the matrix cores), then the
+                # vector-unit kernel (an explicit tile) on the same inputs
+                ts = {}
+                for kind, kw in (("mfma", {}), ("vector", {"epb": 1})):
+                    for _ in range(20):
+                        nbx.ax(ur, Gr, Dr, out=wr, **kw)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(100):
+                        nbx.ax(ur, Gr, Dr, out=wr, **kw)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts[kind] = e0.elapsed_time(e1) * 1e-3 / 100
+                t = ts["mfma"]
                 replay[f"E{Er}"] = {
-                    "N": Nr, "mean_launch_us": round(t * 1e6, 2),
+                    "N": Nr, "kernel": "ax16_mfma_kernel (matrix cores)",
+                    "mean_launch_us": round(t * 1e6, 2),
                     "gflops": round(nbx.ax_flops(Nr, Er) / t / 1e9, 1),
                     "gbs_algorithmic": round(nbx.ax_bytes(Nr, Er) / t / 1e9, 1),
+                    "frac_hbm_peak": round(nbx.ax_bytes(Nr, Er) / t / 1e9 / PEAK_HBM_GBS, 4),
+                    "vector_unit_kernel_us": round(ts["vector"] * 1e6, 2),
+                    "speedup_vs_vector_unit": round(ts["vector"] / t, 3),
                     "working_set_mb": round(nbx.ax_bytes(Nr, Er) / 1e6, 1)}
-                log(f"  AX N=16 E={Er}: {t*1e6:.1f} us")
+                log(f"  AX N=16 E={Er}: {t*1e6:.1f} us (vector-unit kernel "
+                    f"{ts['vector']*1e6:.1f} us)")
                 del ur, Gr, wr
             out["sweep"] = {"solvers": sweep, "ax_n16_paper_sizes": replay}
             torch.cuda.empty_cache()

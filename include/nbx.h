@@ -139,11 +139,17 @@ int nbx_brick_ids(int ex, int ey, int ez, int N, int64_t *gid_host, uint8_t *bnd
  * and arithmetic type of u, G, w: NBX_F64 (double), NBX_F32 (float, FP32
  * arithmetic).  D is always double (converted inside).  u and w must not
  * overlap.  E == 0 is a no-op.  NBX_EINVAL for null pointers, N outside
- * [2,16] or E < 0; NBX_EUNSUPPORTED for other precisions. */
+ * [2,16] or E < 0; NBX_EUNSUPPORTED for other precisions.
+ * FP64 at N = 16 (the paper's element size, Table II) runs the r and s
+ * contractions on the matrix cores (FP64 products, one workgroup per
+ * element); its results agree with the vector-unit kernel (nbx_ax_tiled) to
+ * FP64 rounding, not bit for bit.  Every other (prec, N) runs the vector-unit
+ * kernel with the tile table's tile. */
 int nbx_ax(int prec, const void *u, const void *G, const double *D, int N, int64_t E,
            void *w, void *stream);
 
-/* nbx_ax with an explicit tile: epb elements per workgroup (1, 2, 4 or 8).
+/* nbx_ax with an explicit tile: epb elements per workgroup (1, 2, 4 or 8)
+ * of the vector-unit kernel, at every N (FP64 N = 16 included).
  * Every tile computes bit-identical results; tiles differ only in speed.
  * NBX_EINVAL for another epb, NBX_EUNSUPPORTED if the tile's LDS would
  * exceed 160 KB or its workgroup 1024 threads. */
@@ -153,7 +159,8 @@ int nbx_ax_tiled(int prec, const void *u, const void *G, const double *D, int N,
 /* The same operator on factor pairs Gp[E][3][N^3][2] (see Layouts): three
  * 16-byte factor loads per node instead of six 8-byte ones, the form the
  * solvers use inside a problem.  Results are bit-identical to nbx_ax /
- * nbx_ax_tiled on the same factors.  Arguments and errors as there. */
+ * nbx_ax_tiled on the same factors (FP64 at N = 16 runs nbx_ax's
+ * matrix-core kernel here too).  Arguments and errors as there. */
 int nbx_ax_paired(int prec, const void *u, const void *Gp, const double *D, int N, int64_t E,
                   void *w, void *stream);
 int nbx_ax_paired_tiled(int prec, const void *u, const void *Gp, const double *D, int N,

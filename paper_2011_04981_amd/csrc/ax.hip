@@ -23,6 +23,8 @@ int ax_pcg_launch_f64_tiled(int N, int epb, const double *G, const double *D, in
 int ax_pcg_launch_f32_tiled(int N, int epb, const float *G, const double *D, int64_t E,
                             const float *z, float *p, float *w, double *part,
                             const double *scal, hipStream_t s);
+int ax16_mfma_launch(int planes, const double *u, const double *G, const double *D, double *w,
+                     int64_t E, hipStream_t s);
 int ax_launch_g_f16(int N, int epb, const float *u, const void *G, const float *gscale,
                     const double *D, float *w, int64_t E, hipStream_t s);
 int ax_launch_g_bf16(int N, int epb, const float *u, const void *G, const float *gscale,
@@ -171,6 +173,10 @@ extern "C" int nbx_ax(int prec, const void *u, const void *G, const double *D, i
 {
     const int c = ax_check(prec, u, G, D, N, E, w);
     if (c != 1) return c;
+    // FP64 at N = 16: the r and s contractions on the matrix cores
+    if (prec == NBX_F64 && N == 16)
+        return ax16_mfma_launch(1, (const double *)u, (const double *)G, D, (double *)w, E,
+                                as_stream(stream));
     return ax_planes(prec, u, G, D, N, E, w, ax_tile(prec, N), as_stream(stream));
 }
 
@@ -188,6 +194,9 @@ extern "C" int nbx_ax_paired(int prec, const void *u, const void *Gp, const doub
 {
     const int c = ax_check(prec, u, Gp, D, N, E, w);
     if (c != 1) return c;
+    if (prec == NBX_F64 && N == 16)
+        return ax16_mfma_launch(0, (const double *)u, (const double *)Gp, D, (double *)w, E,
+                                as_stream(stream));
     return ax_pairs(prec, u, Gp, D, N, E, w, ax_tile(prec, N), as_stream(stream));
 }
 
