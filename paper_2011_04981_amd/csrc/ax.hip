@@ -25,6 +25,8 @@ int ax_pcg_launch_f32_tiled(int N, int epb, const float *G, const double *D, int
                             const double *scal, hipStream_t s);
 int ax16_mfma_launch(int planes, const double *u, const double *G, const double *D, double *w,
                      int64_t E, hipStream_t s);
+int ax16_mfma_pcg_launch(const double *Gp, const double *D, int64_t E, const double *z,
+                         double *p, double *w, double *part, const double *scal, hipStream_t s);
 int ax_launch_g_f16(int N, int epb, const float *u, const void *G, const float *gscale,
                     const double *D, float *w, int64_t E, hipStream_t s);
 int ax_launch_g_bf16(int N, int epb, const float *u, const void *G, const float *gscale,
@@ -106,6 +108,9 @@ int ax_launch_f32(const float *u, const float *G, const double *D, int N, int64_
 int ax_pcg_launch_f64(const double *G, const double *D, int N, int64_t E, const double *z,
                       double *p, double *w, double *part, const double *scal, hipStream_t s)
 {
+    // N = 16: the matrix-core body, one element and one partial per
+    // workgroup (the only tile that fits there, so ax_blocks agrees)
+    if (N == 16) return ax16_mfma_pcg_launch(G, D, E, z, p, w, part, scal, s);
     return ax_pcg_launch_f64_tiled(N, pcg_tile(NBX_F64, N), G, D, E, z, p, w, part, scal, s);
 }
 

@@ -26,6 +26,7 @@
 #include "solver.hpp"
 #include "solver_kernels.hpp"
 #include "ax_kernel.hpp"
+#include "ax16_mfma.hpp"
 #include "gs_kernels.hpp"
 
 #include <algorithm>
@@ -102,6 +103,17 @@ b_ax_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
     const BDesc &d = desc[en.pid];
     ax_body<double, N, EPB, true>(gp(d.z), gp(d.G), dp<double, N>(d.D), gp(d.w), gp(d.p),
                                   gp(d.part1), gp(d.scal), d.E, en.blk);
+}
+
+// N = 16: the standalone solver's matrix-core body, so a batched problem
+// computes the standalone solve's bits
+__global__ void __launch_bounds__(256, 2)
+b_ax16_kernel(const BDesc *__restrict__ desc, const BEntry *__restrict__ tab)
+{
+    const BEntry en = tab[blockIdx.x];
+    const BDesc &d = desc[en.pid];
+    ax16::body<false, true>(gp(d.z), gp(d.G), gp(d.D), gp(d.w), gp(d.p), gp(d.part1),
+                            gp(d.scal), en.blk);
 }
 
 __global__ void __launch_bounds__(1024) b_pap_kernel(const BDesc *__restrict__ desc)
@@ -270,6 +282,11 @@ int launch_b_ax(int epb, const BDesc *desc, const BEntry *tab, int nblk, hipStre
 
 int launch_b_ax_n(int N, int epb, const BDesc *desc, const BEntry *tab, int nblk, hipStream_t s)
 {
+    if (N == 16) {
+        if (epb != 1) return NBX_EUNSUPPORTED;
+        hipLaunchKernelGGL(b_ax16_kernel, dim3(nblk), dim3(256), 0, s, desc, tab);
+        return NBX_OK;
+    }
     switch (N) {
 #define NBX_BAXN(NN) case NN: return launch_b_ax<NN>(epb, desc, tab, nblk, s);
         NBX_BAXN(2) NBX_BAXN(3) NBX_BAXN(4) NBX_BAXN(5) NBX_BAXN(6) NBX_BAXN(7) NBX_BAXN(8)

@@ -206,11 +206,21 @@ def _gpu_state(st, x, r, p, rho):
     return xs, rs, zs, ps, scal
 
 
-@pytest.mark.parametrize("case", ["c1", "deformed8"])
+@pytest.mark.parametrize("case", ["c1", "deformed8", "deformed16"])
 def test_pcg_one_step_parity(case):
-    b = S.c1_brick() if case == "c1" else S.scaled_c2_brick(3, 8)
+    """One fused iteration from the oracle's state at k = 0 ... 99; at
+    N = 16 the fused first stage is the matrix-core body, run on the
+    oracle's own factors (the two sides' factors agree to 1e-12, and at
+    N = 16 the derivative stencil lifts their last-bit differences to
+    ~1e-12 in AX: test_ax16_on_deformed_geometry)."""
+    b = {"c1": S.c1_brick, "deformed8": lambda: S.scaled_c2_brick(3, 8),
+         "deformed16": lambda: S.scaled_c2_brick(2, 16)}[case]()
     P = O.setup(b)
-    st = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array())
+    if case == "deformed16":
+        gid, bnd = nbx.brick_ids(b.ex, b.ey, b.ez, b.N)
+        prob = nbx.Problem(cuda(P.G), nbx.deriv_device(b.N), b.N, nbx.GS(gid, bnd))
+    else:
+        prob = nbx.setup_brick(b.ex, b.ey, b.ez, b.N, b.deform_array()).problem
     state = O.pcg_start(P)
     done = 0
     for k in (0, 1, 10, 50, 99):
@@ -219,8 +229,8 @@ def test_pcg_one_step_parity(case):
             state = (x, r, z, p, rho)
             done = k
         print(f"one-step parity {case} k={k}", flush=True)
-        xs, rs, zs, ps, scal = _gpu_state(st, state[0], state[1], state[3], state[4])
-        st.problem.pcg_iterate(xs, rs, zs, ps, scal, 1)
+        xs, rs, zs, ps, scal = _gpu_state(prob, state[0], state[1], state[3], state[4])
+        prob.pcg_iterate(xs, rs, zs, ps, scal, 1)
         x1, r1, z1, p1, rho1, it, flag, _ = O.pcg_iterate(P, state, 1)
         sc = host(scal)
         assert sc[nbx.S_FLAG] == 0 and sc[nbx.S_ITER] == 1

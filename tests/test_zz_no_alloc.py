@@ -41,7 +41,7 @@ def _cuda(a):
     return torch.as_tensor(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("order", [(6, 10), (8, 6)])
+@pytest.mark.parametrize("order", [(6, 10), (8, 6), (16, 8)])
 def test_noalloc_iterations_equal_the_allocating_entry_point(order):
     """Two calls in a row: a 6x5x4 brick, then a smaller problem (3x3x2,
     fewer local nodes in both orders)."""
