@@ -515,6 +515,27 @@ def main():
                 sweep[f"N{Ns}"] = {"E": E, "local_nodes": E * Ns ** 3, **row}
                 del st, x64, xs
                 torch.cuda.empty_cache()
+            if not a.no_pcg:
+                # the paper's element size in a solve: FP64 Jacobi-PCG on the
+                # C2 deformation over a 20^3 brick at N = 16 (E = 8000, the
+                # replay's larger size; the fused stage on the matrix cores)
+                b16 = S.scaled_c2_brick(20, 16)
+                log(f"sweep: N=16, E={b16.E}")
+                st = nbx.setup_brick(b16.ex, b16.ey, b16.ez, 16, b16.deform_array())
+                stream.synchronize()
+                st.problem.pcg(st.b, rtol=1e-10, max_iter=20000, check_every=20)
+                times = []
+                for _ in range(2):
+                    h0 = time.perf_counter()
+                    _, rs = st.problem.pcg(st.b, rtol=1e-10, max_iter=20000, check_every=20)
+                    times.append(time.perf_counter() - h0)
+                sweep["N16"] = {"E": b16.E, "local_nodes": b16.E * 16 ** 3,
+                                "fp64": {"iters": rs.iters, "seconds": round(min(times), 5),
+                                         "ms_per_iter": round(min(times) / rs.iters * 1e3, 4),
+                                         "true_relres": rs.true_relres, "status": rs.status}}
+                log(f"  N=16 fp64: {rs.iters} it, {min(times):.3f} s")
+                del st
+                torch.cuda.empty_cache()
             replay = {}
             for Er in (800, 8000):
                 Nr = 16
