@@ -567,6 +567,12 @@ def main():
                     "vector_unit_kernel_us": round(ts["vector"] * 1e6, 2),
                     "speedup_vs_vector_unit": round(ts["vector"] / t, 3),
                     "working_set_mb": round(nbx.ax_bytes(Nr, Er) / 1e6, 1)}
+                if Er == 800:
+                    # the paper's own measurement (FP64 AX, 16 points per
+                    # direction, E = 800; Table II and Section IV), other
+                    # hardware: context for this line, not its target
+                    replay["E800"]["paper_context_gflops"] = {
+                        "V100": 407.62, "U280_4_kernels": 289.02, "Xeon_8260M_24_cores": 65.74}
                 log(f"  AX N=16 E={Er}: {t*1e6:.1f} us (vector-unit kernel "
                     f"{ts['vector']*1e6:.1f} us)")
                 del ur, Gr, wr
