@@ -29,10 +29,12 @@
 //      + gr D         A = gr[c][4s+g] (transposed through LDS)  B = D[4s+g][c]
 //      + sum_m D[m][k] gt_m            vector FMAs, gt_m read from LDS
 // LDS slabs are 16x16 with row j's entries permuted by i -> i ^ (j & 14):
-// a row read (16 lanes, one row) and a column read (16 lanes, one column)
-// both touch distinct banks in each half-wave.  gt of slab k is written over
-// u's slab k once every wave has read u for its t contraction and the
-// owning wave has taken slab k's r and s products.  Measured at E = 8000
+// a half-wave's row reads (two whole rows) and column reads (two columns of
+// all 16 rows) both touch 32 distinct 8-byte bank pairs.  In the plain
+// operator gt of slab k is written over u's slab k once every wave has read
+// u for its t contraction and the owning wave has taken slab k's r and s
+// products; the fused stage keeps p in u's slabs for <p, w> and writes gt
+// to slabs of its own (72 KB, two workgroups per CU).  Measured at E = 8000
 // against a kernel with padded 17-double rows, separate gt slabs and the
 // next slab's factors prefetched (76 KB, 209 VGPRs, two workgroups per
 // CU): 306 against 310-317 us, same bits.
