@@ -240,3 +240,19 @@ def test_autotuner_picks_a_valid_tile_and_is_result_neutral():
         assert set(row["us"]) <= {"1", "2", "4", "8"} and all(v > 0 for v in row["us"].values())
     finally:
         nbx.set_tile(nbx.F64, 8, old)
+
+
+def test_breakdown_at_n16_standalone_and_batched():
+    """At N = 16 the fused first stage (matrix cores) supplies <p, Ap> to
+    the breakdown test: with negated factors the standalone and the batched
+    FP64 solves both stop at once with the breakdown flag, at the same
+    iteration and with the same x."""
+    b = S.scaled_c2_brick(2, 16)
+    st = nbx.setup_brick(b.ex, b.ey, b.ez, 16, b.deform_array())
+    bad = nbx.Problem(-st.G, st.D, 16, st.gs)
+    x, r = bad.pcg(st.b, rtol=1e-10, max_iter=500, check_every=5)
+    print(f"N = 16 indefinite: status {r.status}, flag {r.flag}, {r.iters} it")
+    assert r.status == -5 and r.flag == 2 and r.iters <= 5
+    xs, res, _ = nbx.pcg_batched([bad], [st.b], rtol=1e-10, max_iter=500, check_every=5)
+    assert res[0].flag == 2 and res[0].iters == r.iters
+    assert np.array_equal(host(xs[0]), host(x))
